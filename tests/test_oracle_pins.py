@@ -1,0 +1,549 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test ties an oracle function to something other than itself: a
+hand-derived closed form, brute-force enumeration, a KKT condition checked
+by an independent numerical minimiser, a textbook special case, a theorem
+(monotone free energy for d > L, Sec. 3.2), a library routine, or finite
+differences.  No GPU is involved.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.optimize
+import torch
+
+import oracle as O
+from paper_1511_06103_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_ell(rng, L, N, scale=1.0):
+    return O.normalise(scale * rng.standard_normal((L, N)))
+
+
+def _model_from(inst, b=0):
+    u = inst.unary[b].astype(np.float64)
+    if inst.graph in (synth.GRID4, synth.GRID8):
+        conn = 4 if inst.graph == synth.GRID4 else 8
+        if inst.compat == synth.COMPAT_POTTS:
+            return O.grid_model(u, inst.height, inst.width, conn, potts_w=inst.potts_w)
+        return O.grid_model(u, inst.height, inst.width, conn, theta=inst.theta.astype(np.float64))
+    if inst.graph == synth.CSR:
+        return O.csr_model(u, inst.row_ptr, inst.col, inst.csr_w, theta=inst.theta.astype(np.float64))
+    K = O.round_to_bf16(O.gaussian_kernel(inst.features))
+    return O.dense_model(u, K, potts_w=inst.potts_w, cooc=inst.cooc)
+
+
+# ---------------------------------------------------------------------------
+# graph construction
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("h,w", [(3, 3), (4, 7), (32, 32)])
+def test_grid_edge_counts(h, w):
+    assert O.grid_edges(h, w, 4).shape[0] == h * (w - 1) + (h - 1) * w
+    assert O.grid_edges(h, w, 8).shape[0] == h * (w - 1) + (h - 1) * w + 2 * (h - 1) * (w - 1)
+
+
+def test_grid_edges_workload_sizes():
+    assert O.grid_edges(32, 32, 4).shape[0] == 1984
+    # 256 x 256, 8-connected: 2 * 256 * 255 axis edges + 2 * 255^2 diagonals
+    assert 2 * 256 * 255 + 2 * 255 * 255 == 260610
+
+
+def test_grid_neighbour_sets_by_hand():
+    def nbrs(edges, i):
+        return sorted({int(b) for a, b in edges if a == i} | {int(a) for a, b in edges if b == i})
+    e4, e8 = O.grid_edges(3, 3, 4), O.grid_edges(3, 3, 8)
+    # node layout 0 1 2 / 3 4 5 / 6 7 8
+    assert nbrs(e4, 4) == [1, 3, 5, 7]
+    assert nbrs(e8, 4) == [0, 1, 2, 3, 5, 6, 7, 8]
+    assert nbrs(e4, 0) == [1, 3]
+    assert nbrs(e8, 0) == [1, 3, 4]
+    assert nbrs(e8, 2) == [1, 4, 5]
+    assert nbrs(e8, 7) == [3, 4, 5, 6, 8]
+
+
+def test_csr_model_equals_grid_model():
+    rng = np.random.default_rng(0)
+    h, w, L = 5, 6, 3
+    theta = synth.symmetric_zero_diag(rng, L, 0, 2).astype(np.float64)
+    u = rng.standard_normal((L, h * w))
+    g = O.grid_model(u, h, w, 8, theta=theta)
+    N = h * w
+    rows = [[] for _ in range(N)]
+    for a, b in g.edges:
+        rows[a].append(b)
+        rows[b].append(a)
+    row_ptr = np.cumsum([0] + [len(r) for r in rows])
+    col = np.concatenate([sorted(r) for r in rows])
+    c = O.csr_model(u, row_ptr, col, None, theta=theta)
+    ell = _rand_ell(rng, L, N)
+    np.testing.assert_allclose(O.messages(ell, c), O.messages(ell, g), atol=1e-14)
+    assert abs(O.free_energy(ell, c) - O.free_energy(ell, g)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# hand-derived two-node example (Eq. 2, 5, 7, 13-15)
+# ---------------------------------------------------------------------------
+
+def _two_node():
+    g = json.load(open(os.path.join(GOLDEN, "two_node_potts.json")))
+    u = np.array(g["unary"], dtype=np.float64)
+    return g, O.grid_model(u, 1, 2, 4, potts_w=g["potts_w"])
+
+
+def test_two_node_closed_forms():
+    g, model = _two_node()
+    # state energies from the definition: u_0(x0) + u_1(x1) + w [x0 != x1]
+    # (0,0): 0 + 0.5 + 0 ; (0,1): 0 + 0 + 1 ; (1,0): 1 + 0.5 + 1 ; (1,1): 1 + 0 + 0
+    E = {(0, 0): 0.5, (0, 1): 1.0, (1, 0): 2.5, (1, 1): 1.0}
+    log_z = math.log(sum(math.exp(-e) for e in E.values()))
+    lz, marg, _, _ = O.brute_force(model)
+    assert abs(lz - log_z) < 1e-14
+    p00 = math.exp(-0.5 - log_z) + math.exp(-1.0 - log_z)
+    assert abs(marg[0, 0] - p00) < 1e-14
+
+    # uniform q: F = mean energy - 2 log 2
+    ell_u = np.full((2, 2), -math.log(2))
+    assert abs(O.free_energy(ell_u, model) - (sum(E.values()) / 4 - 2 * math.log(2))) < 1e-14
+
+    q = np.array(g["q_test"])
+    Q = {(a, b): q[a, 0] * q[b, 1] for a in (0, 1) for b in (0, 1)}
+    mean_e = sum(Q[s] * E[s] for s in E)
+    neg_h = sum(v * math.log(v) for v in q.ravel())
+    F = mean_e + neg_h
+    assert abs(O.free_energy(np.log(q), model) - F) < 1e-14
+    # KL(Q||P) = F + log Z  (Eq. 5 and 7)
+    kl = sum(Q[s] * (math.log(Q[s]) + E[s] + log_z) for s in E)
+    assert abs(O.kl_divergence(np.log(q), model) - kl) < 1e-14
+    assert abs(kl - (F + log_z)) < 1e-14
+
+    # messages: m_0 = u_0 + Theta q_1, m_1 = u_1 + Theta q_0, Theta = [[0,1],[1,0]]
+    m = O.messages(np.log(q), model)
+    np.testing.assert_allclose(m[:, 0], [0.0 + q[1, 1], 1.0 + q[0, 1]], atol=1e-15)
+    np.testing.assert_allclose(m[:, 1], [0.5 + q[1, 0], 0.0 + q[0, 0]], atol=1e-15)
+
+    # one step at alpha: q'_i proportional to q_i^(1-alpha) exp(-alpha m_i)  (Eq. 14)
+    a = g["alpha"]
+    new = O.prox_step(np.log(q), model, a)
+    for i in (0, 1):
+        r = q[:, i] ** (1 - a) * np.exp(-a * m[:, i])
+        np.testing.assert_allclose(np.exp(new[:, i]), r / r.sum(), atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# free energy against enumeration (Eq. 5, 7)
+# ---------------------------------------------------------------------------
+
+def test_free_energy_plus_logz_is_kl_3x3():
+    inst = synth.workload_3x3()
+    model = _model_from(inst)
+    bf = O.brute_force(model)
+    log_z = bf[0]
+    rng = np.random.default_rng(3)
+    states = [_rand_ell(rng, 2, 9, s) for s in (0.3, 1.0, 3.0)]
+    states += O.solve(model, 0.2, 15)[::5]
+    for ell in states:
+        kl = O.kl_divergence(ell, model, bf)
+        F = O.free_energy(ell, model)
+        assert abs((F + log_z) - kl) <= 1e-12 * max(1.0, abs(kl))
+        assert kl >= -1e-12          # F >= -log Z
+        q = np.exp(ell)
+        assert abs(O.energy(q, model) - O.energy_edge_sum(q, model)) < 1e-12
+
+
+def test_free_energy_plus_logz_is_kl_theta_8conn():
+    rng = np.random.default_rng(7)
+    L, h, w = 3, 2, 3
+    theta = synth.symmetric_zero_diag(rng, L, 0, 2).astype(np.float64)
+    theta[0, 0] = 0.3   # a diagonal term too (the oracle accepts any compatibility)
+    u = rng.standard_normal((L, h * w))
+    model = O.grid_model(u, h, w, 8, theta=theta)
+    bf = O.brute_force(model)
+    for s in (0.5, 2.0):
+        ell = _rand_ell(rng, L, h * w, s)
+        assert abs(O.free_energy(ell, model) + bf[0] - O.kl_divergence(ell, model, bf)) < 1e-12
+
+
+def test_dense_cooc_free_energy_against_enumeration():
+    rng = np.random.default_rng(5)
+    N, L = 5, 3
+    f = np.concatenate([rng.uniform(0, 3, (N, 2)), rng.uniform(0, 1, (N, 3))], axis=1)
+    K = O.gaussian_kernel(f)
+    cooc = synth.symmetric_zero_diag(rng, L, 0, 1).astype(np.float64)
+    u = rng.standard_normal((L, N))
+    model = O.dense_model(u, K, potts_w=1.0, cooc=cooc)
+    bf = O.brute_force(model)
+    for s in (0.5, 2.0):
+        ell = _rand_ell(rng, L, N, s)
+        q = np.exp(ell)
+        assert abs(O.energy(q, model) - O.energy_edge_sum(q, model)) < 1e-12
+        assert abs(O.free_energy(ell, model) + bf[0] - O.kl_divergence(ell, model, bf)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# message = gradient of the expected energy (theta* of Eq. 15)
+# ---------------------------------------------------------------------------
+
+def _fd_energy_grad(q, model, h=1e-6):
+    g = np.zeros_like(q)
+    for idx in np.ndindex(*q.shape):
+        a, b = q.copy(), q.copy()
+        a[idx] += h
+        b[idx] -= h
+        g[idx] = (O.energy_edge_sum(a, model) - O.energy_edge_sum(b, model)) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("kind", ["grid4_potts", "grid8_theta", "csr", "dense_cooc"])
+def test_message_is_energy_gradient(kind):
+    rng = np.random.default_rng(11)
+    L = 3
+    if kind == "grid4_potts":
+        model = O.grid_model(rng.standard_normal((L, 12)), 3, 4, 4, potts_w=0.7)
+    elif kind == "grid8_theta":
+        th = rng.uniform(0, 2, (L, L))
+        th = th + th.T
+        model = O.grid_model(rng.standard_normal((L, 12)), 4, 3, 8, theta=th)
+    elif kind == "csr":
+        inst = synth.csr_instance(3, 15, L, 4)
+        model = _model_from(inst)
+    else:
+        inst = synth.dense_instance(4, 10, L, pos_high=3.0)
+        model = O.dense_model(inst.unary[0], O.gaussian_kernel(inst.features), potts_w=1.0,
+                              cooc=inst.cooc)
+    q = np.exp(_rand_ell(rng, L, model.n_nodes))
+    m = model.unary + O.pairwise_message(q, model)
+    np.testing.assert_allclose(m, _fd_energy_grad(q, model), atol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# the step solves the per-node proximal problem (Eq. 13)
+# ---------------------------------------------------------------------------
+
+def test_step_satisfies_kkt_and_minimises_prox_objective():
+    inst = synth.grid_theta_random(9, 3, 4, 4, synth.GRID8)
+    model = _model_from(inst)
+    rng = np.random.default_rng(2)
+    ell = _rand_ell(rng, 4, 12, 1.5)
+    for alpha in (0.05, 0.3, 0.5, 1.0):
+        d = 1.0 / alpha - 1.0
+        new = O.prox_step(ell, model, alpha)
+        m = O.messages(ell, model)
+        # KKT: (1 + d) log q' + m - d log q is constant over labels
+        k = (1 + d) * new + m - d * ell
+        assert np.abs(k - k.mean(axis=0, keepdims=True)).max() < 1e-12
+        # independent minimisation of <q, m> - H(q) + d KL(q || q^t) on the simplex
+        for i in range(3):
+            def obj(v):
+                qq = np.exp(v - v.max())
+                qq /= qq.sum()
+                return O.prox_objective(qq, m[:, i], np.exp(ell[:, i]), d)
+            res = scipy.optimize.minimize(obj, np.zeros(4), method="BFGS",
+                                          options={"gtol": 1e-12, "maxiter": 2000})
+            v = res.x
+            q_num = np.exp(v - v.max())
+            q_num /= q_num.sum()
+            np.testing.assert_allclose(np.exp(new[:, i]), q_num, atol=2e-6)
+            assert O.prox_objective(np.exp(new[:, i]), m[:, i], np.exp(ell[:, i]), d) <= res.fun + 1e-12
+
+
+def test_theta_zero_closed_form():
+    rng = np.random.default_rng(4)
+    L, h, w = 5, 4, 6
+    u = rng.standard_normal((L, h * w))
+    model = O.grid_model(u, h, w, 8, theta=np.zeros((L, L)))
+    ell0 = _rand_ell(rng, L, h * w, 2.0)
+    for alpha in (0.2, 0.5):
+        traj = O.solve(model, alpha, 12, ell0=ell0)
+        for t in (1, 5, 12):
+            c = (1 - alpha) ** t
+            np.testing.assert_allclose(traj[t], O.normalise(c * ell0 - (1 - c) * u), atol=1e-13)
+    # alpha = 1 lands on the exact marginals softmax(-u) in one step; KL is then 0
+    one = O.solve(model, 1.0, 1, ell0=ell0)[1]
+    np.testing.assert_allclose(np.exp(one), np.exp(-u) / np.exp(-u).sum(0), atol=1e-14)
+
+
+def test_tiny_theta_zero_kl_is_zero():
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal((2, 6))
+    model = O.grid_model(u, 2, 3, 4, theta=np.zeros((2, 2)))
+    ell = O.solve(model, 1.0, 1, init_mode=1)[1]
+    assert abs(O.kl_divergence(ell, model)) < 1e-12
+
+
+def test_alpha_one_is_naive_parallel():
+    inst = synth.grid_theta_random(12, 6, 5, 4, synth.GRID8)
+    model = _model_from(inst)
+    ell = _rand_ell(np.random.default_rng(0), 4, 30)
+    np.testing.assert_array_equal(O.prox_step(ell, model, 1.0), O.naive_parallel_step(ell, model))
+    # ... and softmax(-m) by the textbook formula
+    m = O.messages(ell, model)
+    np.testing.assert_allclose(np.exp(O.prox_step(ell, model, 1.0)),
+                               np.exp(-m) / np.exp(-m).sum(0), rtol=1e-13)
+
+
+def test_normalisation_every_iterate():
+    inst = synth.grid_theta_random(13, 16, 16, 21, synth.GRID8, iters=20)
+    model = _model_from(inst)
+    for ell in O.solve(model, 0.5, 20):
+        assert np.abs(np.exp(ell).sum(0) - 1).max() < 1e-12
+
+
+def test_normalise_matches_library_log_softmax():
+    z = np.random.default_rng(1).standard_normal((21, 50)) * 30
+    np.testing.assert_allclose(O.normalise(z), scipy.special.log_softmax(z, axis=0), atol=1e-12)
+
+
+def test_init_modes():
+    u = np.random.default_rng(2).standard_normal((4, 7))
+    np.testing.assert_allclose(np.exp(O.init_state(u, 0)), scipy.special.softmax(-u, axis=0), atol=1e-15)
+    np.testing.assert_allclose(np.exp(O.init_state(u, 1)), 0.25, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Lipschitz constant (Sec. 3.2) and monotone free energy for d > L
+# ---------------------------------------------------------------------------
+
+def _adjacency(h, w, conn):
+    A = np.zeros((h * w, h * w))
+    for a, b in O.grid_edges(h, w, conn):
+        A[a, b] = A[b, a] = 1
+    return A
+
+
+@pytest.mark.parametrize("h,w,conn", [(3, 3, 4), (4, 6, 8), (5, 3, 4), (7, 7, 8)])
+def test_adjacency_closed_form_matches_eigvalsh(h, w, conn):
+    np.testing.assert_allclose(np.sort(O.adjacency_eigs_grid(h, w, conn)),
+                               np.linalg.eigvalsh(_adjacency(h, w, conn)), atol=1e-12)
+
+
+def test_lipschitz_constants_of_the_potts_workloads():
+    # 32 x 32 4-connected Potts w=1: L = -lambda_min(A) = 4 cos(pi / 33)
+    assert abs(O.lipschitz_grid(32, 32, 4, O.potts_theta(2, 1.0)) - 4 * math.cos(math.pi / 33)) < 1e-12
+    assert abs(4 * math.cos(math.pi / 33) - 3.981888) < 1e-6
+    assert abs(O.lipschitz_grid(3, 3, 4, O.potts_theta(2, 1.0)) - 2 * math.sqrt(2)) < 1e-12
+
+
+def test_lipschitz_closed_form_against_dense_tangent_hessian():
+    rng = np.random.default_rng(6)
+    h, w, L = 4, 5, 4
+    th = synth.symmetric_zero_diag(rng, L, 0, 2).astype(np.float64)
+    H = np.kron(_adjacency(h, w, 8), th)            # node-major Hessian of E
+    P = np.kron(np.eye(h * w), np.eye(L) - 1.0 / L)
+    ev = np.linalg.eigvalsh(P @ H @ P)
+    # restrict to the tangent space: drop the h*w zero modes along the all-ones per node
+    U, s, _ = np.linalg.svd(P)
+    B = U[:, : h * w * (L - 1)]
+    lam = np.linalg.eigvalsh(B.T @ H @ B).max()
+    assert abs(O.lipschitz_grid(h, w, 8, th) - lam) < 1e-10
+    assert ev.max() >= lam - 1e-10
+
+
+@pytest.mark.parametrize("which", ["3x3", "c1"])
+def test_power_method_matches_closed_form(which):
+    inst = synth.workload_3x3() if which == "3x3" else synth.workload_c1()
+    model = _model_from(inst)
+    lam, rho = O.lipschitz_power(model, iters=6000)
+    exact = O.lipschitz_grid(inst.height, inst.width, 4, O.potts_theta(2, 1.0))
+    assert abs(lam - exact) <= 1e-6 * exact
+    assert rho >= exact - 1e-9
+
+
+def test_power_method_theta_grid8():
+    inst = synth.grid_theta_random(21, 10, 9, 5, synth.GRID8)
+    model = _model_from(inst)
+    lam, _ = O.lipschitz_power(model, iters=8000)
+    exact = O.lipschitz_grid(10, 9, 8, inst.theta.astype(np.float64))
+    assert abs(lam - exact) <= 1e-6 * exact
+
+
+def _kl_nodes(ell_a, ell_b):
+    return float((np.exp(ell_a) * (ell_a - ell_b)).sum())
+
+
+@pytest.mark.parametrize("which", ["c1", "3x3", "theta64", "batch_shape", "dense"])
+def test_free_energy_monotone_at_admissible_alpha(which):
+    if which == "c1":
+        inst, iters = synth.workload_c1(), 50
+    elif which == "3x3":
+        inst, iters = synth.workload_3x3(), 50
+    elif which == "theta64":        # the 256 x 256 L = 21 recipe on a 64 x 64 grid
+        inst, iters = synth.grid_theta_random(2, 64, 64, 21, synth.GRID8), 30
+    elif which == "batch_shape":    # the 128 x 128 batch recipe, one member, 10 steps
+        inst, iters = synth.workload_c5(), 10
+    else:
+        inst, iters = synth.dense_instance(3, 512, 21), 20
+    model = _model_from(inst)
+    if inst.graph == synth.DENSE:
+        lip, _ = O.lipschitz_power(model, iters=400)
+        lip *= 1.02   # power-method estimate from below; extra margin
+    else:
+        conn = 4 if inst.graph == synth.GRID4 else 8
+        th = O.potts_theta(inst.n_labels, inst.potts_w) if inst.compat == synth.COMPAT_POTTS \
+            else inst.theta.astype(np.float64)
+        lip = O.lipschitz_grid(inst.height, inst.width, conn, th)
+    alpha = O.admissible_alpha(lip)
+    d = 1 / alpha - 1
+    traj = O.solve(model, alpha, iters)
+    F = [O.free_energy(e, model) for e in traj]
+    for t in range(iters):
+        # F(q^{t+1}) <= F(q^t) - (d - L) KL(q^{t+1} || q^t)   (Sec. 3.2, d > L)
+        bound = F[t] - (d - lip) * _kl_nodes(traj[t + 1], traj[t])
+        assert F[t + 1] <= bound + 1e-12 * abs(F[t]), (t, F[t], F[t + 1])
+
+
+def test_undamped_parallel_oscillates_on_workload_c1():
+    """The fully parallel update is not monotone on the 32 x 32 Potts grid (Sec. 2.2.2)."""
+    model = _model_from(synth.workload_c1())
+    traj = O.solve(model, 1.0, 50)
+    F = np.array([O.free_energy(e, model) for e in traj])
+    assert (np.diff(F) > 1e-9).sum() > 0
+
+
+# ---------------------------------------------------------------------------
+# fixed points agree with sequential mean field (Eq. 8 vs Eq. 15)
+# ---------------------------------------------------------------------------
+
+def test_parallel_fixed_point_is_sweep_fixed_point():
+    inst = synth.workload_c1()
+    model = _model_from(inst)
+    lip = O.lipschitz_grid(32, 32, 4, O.potts_theta(2, 1.0))
+    alpha = O.admissible_alpha(lip)
+    ell = O.init_state(model.unary)
+    for it in range(20000):
+        new = O.prox_step(ell, model, alpha)
+        if np.abs(new - ell).max() < 1e-12:
+            ell = new
+            break
+        ell = new
+    assert np.abs(O.prox_step(ell, model, alpha) - ell).max() < 1e-11
+    after = O.sweep(ell, model, 1)
+    assert np.abs(np.exp(after) - np.exp(ell)).max() < 1e-9
+
+
+def test_convex_regime_parallel_and_sweep_agree():
+    # w = 0.4 on the 32 x 32 4-connected grid: lambda_min of the tangent Hessian is
+    # -0.4 * 3.98 > -2, and the negative entropy has curvature >= 2 on the tangent
+    # space, so F is strictly convex and has one minimiser.
+    inst = synth.grid_potts_normal(1, 32, 2, synth.GRID4, w=0.4)
+    model = _model_from(inst)
+    lip = O.lipschitz_grid(32, 32, 4, O.potts_theta(2, 0.4))
+    alpha = O.admissible_alpha(lip)
+    ell = O.init_state(model.unary)
+    for _ in range(3000):
+        ell = O.prox_step(ell, model, alpha)
+    sw = O.sweep(O.init_state(model.unary), model, 200)
+    assert np.abs(np.exp(ell) - np.exp(sw)).max() < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# reverse pass against finite differences
+# ---------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_adjoint_matches_finite_differences_fd_instance():
+    inst = synth.workload_fd()
+    model = _model_from(inst)
+    c = synth.adjoint_loss_weights(56, (inst.n_labels, inst.n_nodes)).astype(np.float64)
+    T = inst.iters
+    ell_T = O.solve(model, inst.alpha, T)[-1]
+    gu, gt = O.adjoint(model, inst.alpha, T, c * np.exp(ell_T))
+    fu, ft = O.fd_grad(model, inst.alpha, T, c, eps=1e-3)
+    scale = max(np.abs(fu).max(), np.abs(ft).max())
+    assert np.abs(gu - fu).max() <= 1e-5 * scale
+    assert np.abs(gt - ft).max() <= 1e-5 * scale
+
+
+def test_adjoint_dense_cooc_small():
+    inst = synth.dense_instance(8, 6, 3, pos_high=2.0, iters=4)
+    model = O.dense_model(inst.unary[0], O.gaussian_kernel(inst.features), potts_w=1.0, cooc=inst.cooc)
+    c = synth.adjoint_loss_weights(9, (3, 6)).astype(np.float64)
+    ell_T = O.solve(model, 0.5, 4)[-1]
+    gu, gt = O.adjoint(model, 0.5, 4, c * np.exp(ell_T))
+    fu, ft = O.fd_grad(model, 0.5, 4, c, eps=1e-4)
+    np.testing.assert_allclose(gu, fu, atol=1e-7)
+    np.testing.assert_allclose(gt, ft, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# helpers pinned to library routines
+# ---------------------------------------------------------------------------
+
+def test_round_to_bf16_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        np.exp(-rng.uniform(0, 40, 20000))])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(O.round_to_bf16(x), ref)
+
+
+def test_gaussian_kernel_matches_cdist():
+    import scipy.spatial.distance as D
+    f = np.random.default_rng(1).uniform(0, 5, (40, 5))
+    K = np.exp(-0.5 * D.cdist(f, f, "sqeuclidean"))
+    np.fill_diagonal(K, 0)
+    np.testing.assert_allclose(O.gaussian_kernel(f), K, rtol=1e-13, atol=1e-300)
+
+
+# ---------------------------------------------------------------------------
+# variants and baselines (Sec. 2.2.2, 3.3-3.5)
+# ---------------------------------------------------------------------------
+
+def test_variant_special_cases():
+    inst = synth.grid_potts_normal(31, 6, 2, synth.GRID4)
+    model = _model_from(inst)
+    ell = _rand_ell(np.random.default_rng(3), 2, 36)
+    naive = O.naive_parallel_step(ell, model)
+    # ADHOC with eta = 1 and ADAPTIVE with d = 0 are the naive parallel update
+    np.testing.assert_allclose(O.adhoc_step(ell, model, 1.0), naive, atol=1e-14)
+    np.testing.assert_allclose(O.adaptive_binary_step(ell, model, 0.0), naive, atol=1e-14)
+    # ADAPTIVE with q0 q1 d = constant reduces to the fixed step with that d
+    # ADHOC with eta = 0 leaves q unchanged
+    np.testing.assert_allclose(O.adhoc_step(ell, model, 0.0), ell, atol=1e-14)
+    # momentum with gamma1 = 0 is the fixed-step solve
+    a = O.momentum_solve(model, 0.3, 5, gamma1=0.0)
+    b = O.solve(model, 0.3, 5)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, atol=1e-13)
+
+
+def test_adaptive_binary_matches_fixed_step_when_weight_is_uniform():
+    # for q_{i,0} q_{i,1} equal at every node the adaptive eta is one scalar
+    model = O.grid_model(np.zeros((2, 4)), 2, 2, 4, potts_w=1.0)
+    ell = np.log(np.array([[0.3] * 4, [0.7] * 4]))
+    d = 5.0
+    eta = 1 / (1 + 0.21 * d)
+    np.testing.assert_allclose(O.adaptive_binary_step(ell, model, d), O.prox_step(ell, model, eta), atol=1e-14)
+
+
+def test_adam_and_momentum_preserve_fixed_points():
+    # at a fixed point log q* = normalise(-m*) every eta leaves q* unchanged
+    inst = synth.grid_potts_normal(1, 8, 2, synth.GRID4, w=0.4)
+    model = _model_from(inst)
+    ell = O.init_state(model.unary)
+    for _ in range(3000):
+        ell = O.prox_step(ell, model, 0.3)
+    m = O.messages(ell, model)
+    g = m + ell
+    assert np.abs(g - g.mean(0)).max() < 1e-10     # the natural gradient vanishes there
+    for traj in (O.adam_solve(model, 2.0, 5, ell0=ell), O.momentum_solve(model, 0.4, 5, ell0=ell)):
+        for e in traj:
+            assert np.abs(e - ell).max() < 1e-10
+    # away from it ADAM moves, and every iterate stays normalised
+    traj = O.adam_solve(model, 2.0, 5)
+    assert np.abs(traj[-1] - traj[0]).max() > 1e-3
+    for e in traj:
+        assert np.abs(np.exp(e).sum(0) - 1).max() < 1e-12
+
+
+def test_paper_constants_fixture():
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    import inspect
+    assert inspect.signature(O.momentum_solve).parameters["gamma1"].default == c["momentum_gamma1"]
+    assert inspect.signature(O.adam_solve).parameters["gamma2"].default == c["adam_gamma2"]
+    assert inspect.signature(O.adam_solve).parameters["eps"].default == c["adam_epsilon"]
