@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark of the parallel mean-field solve on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+One bench step is one whole solve of the hot path: initialisation from the
+unaries, T parallel proximal steps (neighbour aggregation, compatibility
+product, damped natural-parameter step, per-node normalisation) and the
+write-out of q, on synthetic inputs already resident in HBM.  The default
+workload is the 256 x 256, 8-connected, L = 21 grid with a random symmetric
+Theta, alpha = 0.5 and T = 100 iterations (FP32).
+
+Prints one JSON line: node-label updates/s = B * N * L * T * K / time, with
+p50/p99 solve latency, the roofline of the dominant kernel (the grid step,
+timed per launch with HIP events on the stream it runs on) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+
+Profiling helpers (single GPU):
+    --mode kernel   only the dominant kernel, --launches times (for counters)
+    --mode copy     a plain device-to-device copy of --copy-mib MiB (the
+                    reference that scales FETCH_SIZE / WRITE_SIZE readings)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_UPDATE = 12          # read log q (4) + read u (4) + write log q' (4)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_step_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1511_06103_amd", "csrc", "grid_kernels.hip")
+
+WORKLOADS = {
+    "grid256_L21_theta": lambda s: s.workload_c2(),
+    "grid2048_L21_theta": lambda s: s.workload_big(),
+    "grid32_L2_potts": lambda s: s.workload_c1(),
+    "batch16_grid128_L21": lambda s: s.workload_c5(),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def make_solver(inst, torch, mf):
+    dev = torch.device("cuda:0")
+    u = torch.from_numpy(inst.unary).to(dev)
+    kw = dict(alpha=inst.alpha)
+    if inst.theta is not None:
+        kw["theta"] = torch.from_numpy(inst.theta).to(dev)
+    else:
+        kw["potts_w"] = inst.potts_w
+    graph = "grid4" if inst.graph == 0 else "grid8"
+    return mf.MeanField(u, graph, height=inst.height, width=inst.width, **kw)
+
+
+def time_step_launches(solver, torch, launches):
+    """Average duration of one grid-step launch, HIP events around each launch."""
+    stream = solver.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    with torch.cuda.stream(stream):
+        for a, b in ev:
+            a.record(stream)
+            solver.step(1)
+            b.record(stream)
+    torch.cuda.synchronize()
+    d = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
+    return float(d.mean()), float(np.median(d))
+
+
+def cpu_baseline(inst, budget_s=12.0):
+    """The FP64 oracle, untuned, timed on this host on a bounded sample."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    b = 0
+    conn = 4 if inst.graph == 0 else 8
+    th = None if inst.theta is None else inst.theta.astype(np.float64)
+    pw = None if inst.theta is not None else inst.potts_w
+    model = O.grid_model(inst.unary[b].astype(np.float64), inst.height, inst.width, conn, theta=th, potts_w=pw)
+    with threadpool_limits(1):
+        ell = O.init_state(model.unary)
+        O.prox_step(ell, model, inst.alpha)     # build caches outside the timing
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            ell = O.prox_step(ell, model, inst.alpha)
+            steps += 1
+        el = time.perf_counter() - t0
+    L, N = model.unary.shape
+    return {"value": steps * N * L / el, "unit": "node-label updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 proximal steps of one {inst.height}x{inst.width} L={L} problem "
+                      f"({el:.1f} s, 1 thread)"}
+
+
+def load_traffic(algo_bytes_per_launch):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid256_L21_theta", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "copy"])
+    ap.add_argument("--launches", type=int, default=200)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
+              "(a grid would shard into row slabs with one halo exchange per step).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1511_06103_amd import mf, synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    mf.lib()
+    torch.cuda.set_device(0)
+
+    if args.mode == "copy":
+        n = args.copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for i in range(5):
+            b.copy_(a)
+            torch.cuda.synchronize()
+            log(f"copy {i}: {args.copy_mib} MiB")
+        return
+
+    inst = WORKLOADS[args.workload](synth)
+    B, L, N = inst.unary.shape
+    T = inst.iters
+    log(f"workload {inst.name}: B={B} N={N} L={L} T={T} alpha={inst.alpha}")
+    solver = make_solver(inst, torch, mf)
+    q = torch.empty_like(solver.unary)
+
+    if args.mode == "kernel":
+        solver.solve(0)
+        for i in range(args.launches):
+            solver.step(1)
+        torch.cuda.synchronize()
+        log(f"kernel mode: {args.launches} step launches done")
+        return
+
+    for i in range(args.warmup):
+        solver.solve(T, q)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(solver.stream)
+        solver.solve(T, q)
+        ends[i].record(solver.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])    # ms
+    ev_total = starts[0].elapsed_time(ends[-1]) * 1e-3
+    total = wall
+    updates = B * N * L * T * args.steps
+    value = updates / total
+    log(f"timed {args.steps} solves: wall {wall * 1e3:.3f} ms, HIP events {ev_total * 1e3:.3f} ms")
+
+    # dominant kernel: one grid-step launch over all B * N * L node-labels
+    mean_d, med_d = time_step_launches(solver, torch, args.launches)
+    algo = BYTES_PER_UPDATE * B * N * L
+    achieved = algo / mean_d / 1e9
+    traffic = load_traffic(algo)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "grid_step_kernel", "launch_us_mean": round(mean_d * 1e6, 3),
+                "launch_us_median": round(med_d * 1e6, 3), "algorithmic_bytes_per_launch": algo}
+    log(f"grid step: {mean_d * 1e6:.2f} us mean, {med_d * 1e6:.2f} us median per launch -> {achieved:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(inst)
+        log(f"cpu oracle: {cpu['value']:.3e} updates/s ({cpu['sample']})")
+
+    out = {
+        "metric": "node-label updates/s (N*L*iters/s) at oracle-matched marginals",
+        "value": value,
+        "unit": "node-label updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total * 1e3 / args.steps,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": inst.name, "height": inst.height, "width": inst.width, "labels": L,
+                   "batch": B, "connectivity": 4 if inst.graph == 0 else 8,
+                   "compat": "theta" if inst.theta is not None else "potts", "alpha": inst.alpha,
+                   "iters": T, "step": "init + iters proximal steps + write q"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * mf.h -- C ABI of the MI355X parallel mean-field library (libmf.so).
+ *
+ * The library runs the proximal-gradient parallel mean-field update of
+ * Baque, Bagautdinov, Fleuret and Fua, "Principled Parallel Mean-Field
+ * Inference for Discrete Random Fields":
+ *
+ *   m_i     = u_i + Theta S_i,      S_i = sum_{j in N(i)} w_ij q_j
+ *   log q_i <- (1 - alpha) log q_i - alpha m_i, renormalised per node
+ *
+ * that is, the damped natural-parameter step of Eq. 15 (Sec. 3.1) with the
+ * fixed step size alpha = eta = 1 / (1 + d) of Eq. 16 (Sec. 3.2), applied to
+ * every node at once.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Energies.  Unaries u and compatibilities Theta are energies:
+ *   P(x) is proportional to exp(-sum_i u_i(x_i) - sum_{(i,j)} w_ij Theta(x_i, x_j)),
+ *   the pairwise model of Eq. 2 (Sec. 2.1) written with the sign of the
+ *   natural parameters of Eq. 6.  Theta must be symmetric for the free
+ *   energy and the convergence guarantee to hold.
+ * - Layout.  Every per-node array is label-major and batch-outermost:
+ *   element (b, l, n) of a [B][L][N] array is at ((b * L) + l) * N + n, with
+ *   n = y * width + x on grids.  Theta is [L][L] row-major, Theta[l][k]
+ *   being the energy of (x_i = l, x_j = k).
+ * - Memory.  All array arguments are device pointers owned by the caller
+ *   (HIP device memory, e.g. PyTorch tensors); they must stay valid until
+ *   the work enqueued on them has completed and, for the pointers stored
+ *   in an mf_desc, until mf_destroy.  The library never allocates device
+ *   memory: scratch space is the caller's workspace buffer, sized by
+ *   mf_workspace_size.  The library owns only the host-side handle.
+ * - Streams.  Work is enqueued asynchronously on the caller's hipStream_t
+ *   (desc.stream, NULL = the default stream).  Only mf_free_energy and
+ *   mf_check synchronise that stream.
+ * - Errors.  Every entry point returns an mf_status; nothing throws or
+ *   aborts across the ABI.  Arguments are validated on the host before any
+ *   launch.  mf_last_error gives a message for the last failure.
+ */
+#ifndef MF_H_
+#define MF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MF_ABI_VERSION 1
+#define MF_MAX_LABELS 32   /* largest label count the step kernels accept */
+
+typedef enum {
+  MF_OK = 0,
+  MF_EINVAL = -1,         /* invalid argument; nothing was enqueued */
+  MF_ENONFINITE = -2,     /* a non-finite unary or state was detected on the device */
+  MF_EDEVICE = -3,        /* a HIP call or kernel launch failed */
+  MF_EUNSUPPORTED = -4,   /* valid but not implemented (e.g. L > MF_MAX_LABELS) */
+  MF_ENOWORKSPACE = -5    /* workspace missing or smaller than mf_workspace_size */
+} mf_status;
+
+/* Graph of the random field.  Grids have a free (non-periodic) boundary and
+ * unit weights; 8-connectivity adds both diagonals.  CSR lists, for each
+ * node i, the neighbours j and weights w_ij entering S_i.  DENSE is the fully
+ * connected field with an explicit N x N kernel (Sec. 4.2, semantic
+ * segmentation with a dense CRF). */
+typedef enum { MF_GRID4 = 0, MF_GRID8 = 1, MF_CSR = 2, MF_DENSE = 3 } mf_graph;
+
+/* GENERAL: the full L x L Theta.  POTTS: Theta = potts_w (1 1^T - I). */
+typedef enum { MF_COMPAT_GENERAL = 0, MF_COMPAT_POTTS = 1 } mf_compat;
+
+/* Precision of the neighbour messages.  The state log q, the step and the
+ * log-sum-exp are FP32 in every mode; the *_MSG modes round q to BF16 or
+ * FP16 where it is staged as the operand of the neighbour aggregation
+ * (the dense product runs on MFMA in these modes) and accumulate in FP32. */
+typedef enum { MF_P_F32 = 0, MF_P_BF16MSG = 1, MF_P_F16MSG = 2 } mf_precision;
+
+/* Initial state.  The paper leaves q^0 open.  UNARY: q^0 = softmax(-u).
+ * UNIFORM: q^0 = 1/L.  STATE: state buffer 0 already holds log q^0 written
+ * by the caller (resume from a checkpoint). */
+typedef enum { MF_INIT_UNARY = 0, MF_INIT_UNIFORM = 1, MF_INIT_STATE = 2 } mf_init_mode;
+
+typedef struct mf_desc {
+  int32_t abi_version;     /* must be MF_ABI_VERSION */
+  int32_t batch;           /* B >= 1 problems sharing graph, Theta and alpha */
+  int32_t n_nodes;         /* N >= 1 */
+  int32_t height, width;   /* grids: height * width == n_nodes; ignored otherwise */
+  int32_t n_labels;        /* 1 <= L <= MF_MAX_LABELS */
+  int32_t graph;           /* mf_graph */
+  int32_t compat;          /* mf_compat */
+  int32_t precision;       /* mf_precision */
+  int32_t init;            /* mf_init_mode */
+  double alpha;            /* step size eta = 1 / (1 + d), in (0, 1]; 1 = fully parallel */
+  float potts_w;           /* POTTS weight (any finite value) */
+  int32_t steps_per_launch; /* grids: proximal steps fused into one launch (temporal
+                             * blocking); 0 = chosen by the library, 1 = one step per
+                             * launch; clamped to what the tile fits in LDS */
+  /* CSR graph (graph == MF_CSR): row_ptr [N + 1] non-decreasing from 0,
+   * col [nnz] in [0, N), weights [nnz] or NULL for unit weights.  The free
+   * energy assumes the adjacency is symmetric. */
+  const int32_t *csr_row_ptr;
+  const int32_t *csr_col;
+  const float *csr_w;
+  int64_t csr_nnz;
+  /* Dense graph (graph == MF_DENSE): K is N x N row-major bfloat16 bits
+   * (uint16), symmetric with a zero diagonal; cooc is an optional [L][L]
+   * symmetric co-occurrence energy applied to every pair with weight 1/N. */
+  const uint16_t *dense_K;
+  const float *cooc;
+  const float *unary;      /* [B][L][N] FP32, finite */
+  const float *theta;      /* [L][L] FP32 (GENERAL); ignored for POTTS */
+  float *state;            /* [2][B][L][N] FP32 log q, ping-pong */
+  void *workspace;         /* device scratch of at least mf_workspace_size bytes */
+  size_t workspace_bytes;
+  void *stream;            /* hipStream_t */
+} mf_desc;
+
+typedef struct mf_handle mf_handle;
+
+/* ABI version compiled into the library. */
+int32_t mf_abi_version(void);
+
+/* sizeof(mf_desc) as compiled into the library, for bindings that lay the
+ * descriptor out themselves. */
+size_t mf_desc_size(void);
+
+/* Bytes of device workspace the problem needs (256-byte aligned start
+ * required).  Returns 0 for an invalid descriptor. */
+size_t mf_workspace_size(const mf_desc *d);
+
+/* Host-side validation only: checks every rule that mf_init checks, makes
+ * no HIP call.  MF_OK, MF_EINVAL, MF_EUNSUPPORTED or MF_ENOWORKSPACE. */
+mf_status mf_validate(const mf_desc *d);
+
+/* Validate, create a handle (*out), and enqueue the initialisation of
+ * state buffer 0 according to d->init (Eq. 6: log q^0 = -u - lse(-u) for
+ * MF_INIT_UNARY).  The descriptor is copied; its pointers are borrowed.
+ * A non-finite unary is reported as MF_ENONFINITE by the next mf_check or
+ * mf_free_energy.  On failure *out is NULL and nothing was enqueued. */
+mf_status mf_init(const mf_desc *d, mf_handle **out);
+
+/* Enqueue n_steps >= 0 parallel proximal steps (Eq. 15 with Eq. 16):
+ * every node reads iteration t and writes t + 1 (Jacobi, double-buffered). */
+mf_status mf_step(mf_handle *h, int32_t n_steps);
+
+/* Re-initialise according to d->init, run iters steps, and if q_out is
+ * not NULL write q = exp(log q) to q_out [B][L][N] (device).  With
+ * MF_INIT_STATE the solve starts from whatever buffer 0 holds at the time
+ * of the call (steps write buffers 1 and 0 in turn).  The fixed iteration
+ * count is the stopping rule the paper uses in practice (Sec. 3.1). */
+mf_status mf_solve(mf_handle *h, int32_t iters, float *q_out);
+
+/* Free energy F(q) = E(q) - H(q) of Eq. 7 (Sec. 2.2.1) of the current
+ * state, one FP64 value per batch item written to F_host[B] (host
+ * memory), computed with FP64 arithmetic on the device.  F equals
+ * KL(Q || P) - log Z (Eq. 5).  Synchronises the stream. */
+mf_status mf_free_energy(mf_handle *h, double *F_host);
+
+/* Synchronise the stream and report deferred device errors:
+ * MF_ENONFINITE if a non-finite unary was seen, MF_EDEVICE on a HIP error. */
+mf_status mf_check(mf_handle *h);
+
+/* Device pointer to the current log q, [B][L][N] inside desc.state. */
+const float *mf_current_state(const mf_handle *h);
+
+/* Number of steps taken since the last (re)initialisation. */
+int32_t mf_iteration(const mf_handle *h);
+
+/* Proximal steps the handle fuses into one kernel launch (after the
+ * library's choice and clamping), or -1 for a NULL handle. */
+int32_t mf_steps_per_launch(const mf_handle *h);
+
+/* Destroy the handle (host memory only).  Does not synchronise. */
+void mf_destroy(mf_handle *h);
+
+/* Message for the last failure on h, or of this thread when h is NULL.
+ * Valid until the next call on the same handle / thread. */
+const char *mf_last_error(const mf_handle *h);
+
+/* Build the dense-CRF kernel K_ij = exp(-|f_i - f_j|^2 / 2), K_ii = 0
+ * (the Gaussian kernel of the fully connected CRF, Sec. 4.2), rounded to
+ * bfloat16 (round to nearest even) into K_bf16 [n][n] (device, uint16 bits).
+ * features: device [n][dim] FP32, 1 <= dim <= 16.  Asynchronous. */
+mf_status mf_dense_kernel(const float *features, int32_t n, int32_t dim, uint16_t *K_bf16,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H_ */

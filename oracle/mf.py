@@ -26,10 +26,11 @@ from dataclasses import dataclass
 from typing import List, Optional
 
 import numpy as np
+import scipy.sparse
 
 __all__ = [
     "Model", "potts_theta", "grid_edges", "grid_model", "csr_model", "dense_model", "gaussian_kernel",
-    "round_to_bf16", "normalise", "init_state", "neighbour_sum", "pairwise_message", "messages",
+    "round_to_bf16", "round_to_f16", "normalise", "init_state", "neighbour_sum", "pairwise_message", "messages",
     "prox_step", "prox_objective", "solve", "energy", "energy_edge_sum", "entropy",
     "free_energy", "brute_force", "kl_divergence", "sweep", "naive_parallel_step",
     "adjacency_eigs_grid", "tangent_compat_eigs", "lipschitz_grid", "lipschitz_power",
@@ -66,6 +67,18 @@ class Model:
     @property
     def n_labels(self):
         return self.unary.shape[0]
+
+    def astype(self, dtype):
+        """The same model with its floating-point arrays cast to ``dtype``.
+
+        FP64 is the oracle's precision; an FP32 copy runs the same arithmetic
+        in single precision, which measures how far rounding alone moves an
+        iterate (the floor any FP32 implementation shares).
+        """
+        cast = lambda a: None if a is None else np.asarray(a).astype(dtype)
+        return Model(unary=cast(self.unary), theta=cast(self.theta), arc_dst=self.arc_dst,
+                     arc_src=self.arc_src, arc_w=cast(self.arc_w), edges=self.edges,
+                     edge_w=cast(self.edge_w), K=cast(self.K), cooc=cast(self.cooc))
 
     @property
     def n_nodes(self):
@@ -192,7 +205,7 @@ def normalise(z):
     Implements the proportionality sign of Eq. 14 so that each q_i lies on
     the simplex of Eq. 4.
     """
-    z = np.asarray(z, dtype=np.float64)
+    z = np.asarray(z)
     mx = z.max(axis=0, keepdims=True)
     return z - (mx + np.log(np.exp(z - mx).sum(axis=0, keepdims=True)))
 
@@ -200,21 +213,33 @@ def normalise(z):
 def init_state(unary, mode=0):
     """Initial log q.  The paper does not fix q^0; mode 0 is q^0 = softmax(-u)
     (the mean field of the unaries alone), mode 1 is the uniform distribution."""
-    u = np.asarray(unary, dtype=np.float64)
+    u = np.asarray(unary)
     if mode == 0:
         return normalise(-u)
     if mode == 1:
-        return np.full(u.shape, -np.log(u.shape[0]))
+        return np.full(u.shape, -np.log(u.shape[0]), dtype=u.dtype)
     raise ValueError(mode)
 
 
+def _adjacency(model):
+    """Sparse N x N matrix A with A[dst, src] = sum of the arc weights (built once)."""
+    A = getattr(model, "_A", None)
+    if A is None:
+        N = model.unary.shape[1]
+        A = scipy.sparse.csr_matrix((model.arc_w, (model.arc_dst, model.arc_src)), shape=(N, N),
+                                    dtype=model.arc_w.dtype)
+        model._A = A
+    return A
+
+
 def neighbour_sum(q, model):
-    """S[:, i] = sum over neighbours j of w_ij q[:, j] (sparse) or K @ q (dense)."""
+    """S[:, i] = sum over neighbours j of w_ij q[:, j] (sparse) or K @ q (dense).
+
+    The sparse case is the product with the weighted adjacency matrix.
+    """
     if model.K is not None:
         return q @ model.K.T
-    S = np.zeros_like(q)
-    np.add.at(S.T, model.arc_dst, model.arc_w[:, None] * q[:, model.arc_src].T)
-    return S
+    return np.asarray((_adjacency(model) @ q.T).T)
 
 
 def pairwise_message(q, model):
@@ -233,13 +258,26 @@ def pairwise_message(q, model):
     return out
 
 
-def messages(ell, model):
+def round_to_f16(x):
+    """Round to IEEE binary16 (round to nearest even, via binary32), returned as FP64."""
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+def messages(ell, model, operand=None):
     """m = u + pairwise message at q = exp(ell): the coordinate-wise optimum
-    theta* = -E_{Q/X_i}[log P] of Eq. 15 (Sec. 3.1)."""
-    return model.unary + pairwise_message(np.exp(ell), model)
+    theta* = -E_{Q/X_i}[log P] of Eq. 15 (Sec. 3.1).
+
+    ``operand`` (optional) rounds q where it enters the neighbour aggregation,
+    which is what the reduced-precision message variants compute; the
+    accumulation and everything after it stay in the model's precision.
+    """
+    q = np.exp(ell)
+    if operand is not None:
+        q = operand(q)
+    return model.unary + pairwise_message(q, model)
 
 
-def prox_step(ell, model, alpha):
+def prox_step(ell, model, alpha, operand=None):
     """One parallel KL-proximal step (Eq. 13-15, Sec. 3.1) with D = d I (Eq. 16, Sec. 3.2).
 
     In natural parameters theta^{t+1} = eta theta* + (1 - eta) theta^t with
@@ -247,8 +285,9 @@ def prox_step(ell, model, alpha):
     log q^{t+1} = normalise((1 - alpha) log q^t - alpha m).
     All nodes read iteration t and write t + 1 (a Jacobi update).
     """
-    m = messages(ell, model)
-    return normalise((1.0 - alpha) * ell - alpha * m)
+    m = messages(ell, model, operand)
+    a = ell.dtype.type(alpha)
+    return normalise((ell.dtype.type(1.0) - a) * ell - a * m)
 
 
 def prox_objective(q_new_i, grad_i, q_old_i, d):
@@ -260,15 +299,15 @@ def prox_objective(q_new_i, grad_i, q_old_i, d):
     return float(q @ grad_i + neg_h + d * kl)
 
 
-def solve(model, alpha, iters, init_mode=0, ell0=None):
+def solve(model, alpha, iters, init_mode=0, ell0=None, operand=None):
     """Run ``iters`` parallel proximal steps from q^0; return every iterate (list of [L, N]).
 
     The paper stops after a fixed number of iterations in practice (Sec. 3.1).
     """
-    ell = init_state(model.unary, init_mode) if ell0 is None else np.asarray(ell0, dtype=np.float64)
+    ell = init_state(model.unary, init_mode) if ell0 is None else np.asarray(ell0, dtype=model.unary.dtype)
     out = [ell]
     for _ in range(iters):
-        ell = prox_step(ell, model, alpha)
+        ell = prox_step(ell, model, alpha, operand)
         out.append(ell)
     return out
 
@@ -558,11 +597,10 @@ def adjoint(model, alpha, iters, grad_ell_T, init_mode=0):
 
 
 def _neighbour_sum_transpose(S_bar, model):
+    """Adjoint of neighbour_sum: S_bar @ K (dense) or the product with A^T (sparse)."""
     if model.K is not None:
         return S_bar @ model.K
-    out = np.zeros_like(S_bar)
-    np.add.at(out.T, model.arc_src, model.arc_w[:, None] * S_bar[:, model.arc_dst].T)
-    return out
+    return np.asarray((_adjacency(model).T @ S_bar.T).T)
 
 
 def fd_grad(model, alpha, iters, weights, eps=1e-3, init_mode=0):

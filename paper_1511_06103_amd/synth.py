@@ -9,7 +9,8 @@ can both consume its output without sharing any of the method's arithmetic.
 Every draw uses ``numpy.random.default_rng(seed)`` (PCG64) in FP64, in the
 order documented on each function, and is then rounded to FP32: the values
 a kernel receives are exactly representable, and the oracle widens the same
-FP32 values back to FP64.
+FP32 values back to FP64.  Scalar parameters (step size, Potts weight) are
+rounded to FP32 for the same reason.
 
 Sign convention: unaries and compatibilities are *energies*
 (P(x) proportional to exp(-sum_i u_i(x_i) - sum_edges Theta(x_i, x_j))), the reading
@@ -83,19 +84,25 @@ class Instance:
         return self.unary.shape[0]
 
 
-def grid_potts_normal(seed, side, n_labels=2, conn=GRID4, w=1.0, alpha=0.5, iters=50, name=None):
+def grid_potts_normal(seed, side, n_labels=2, conn=GRID4, w=1.0, alpha=0.5, iters=50, name=None,
+                      width=None, batch=1):
     """Potts grid with iid N(0,1) unaries.
 
-    Draw order: ``standard_normal((L, side, side))``.  Potts weight ``w``.
-    Used for the 32 x 32, L = 2, 4-connected workload (seed 1) and the 3 x 3
-    brute-force instance (seed 11).
+    Draw order: ``standard_normal((L, H, W))`` for a single problem, else
+    ``standard_normal((B, L, H, W))``; H = side, W = width (default side).
+    Potts weight ``w``.  Used for the 32 x 32, L = 2, 4-connected workload
+    (seed 1) and the 3 x 3 brute-force instance (seed 11).
     """
+    height = side
+    width = side if width is None else width
     rng = np.random.default_rng(seed)
-    u = rng.standard_normal((n_labels, side, side))
-    return Instance(name=name or f"potts{side}x{side}L{n_labels}", graph=conn, n_labels=n_labels,
-                    n_nodes=side * side, height=side, width=side,
-                    unary=_f32(u.reshape(1, n_labels, side * side)),
-                    compat=COMPAT_POTTS, potts_w=float(w), alpha=alpha, iters=iters)
+    shape = (n_labels, height, width) if batch == 1 else (batch, n_labels, height, width)
+    u = rng.standard_normal(shape)
+    return Instance(name=name or f"potts{height}x{width}L{n_labels}", graph=conn, n_labels=n_labels,
+                    n_nodes=height * width, height=height, width=width,
+                    unary=_f32(u.reshape(batch, n_labels, height * width)),
+                    compat=COMPAT_POTTS, potts_w=float(np.float32(w)), alpha=float(np.float32(alpha)),
+                    iters=iters)
 
 
 def grid_theta_random(seed, height, width=None, n_labels=21, conn=GRID8, batch=1,
@@ -120,7 +127,7 @@ def grid_theta_random(seed, height, width=None, n_labels=21, conn=GRID8, batch=1
         u = np.ascontiguousarray(np.transpose(u, (1, 0, 2, 3))).reshape(batch, n_labels, height * width)
     return Instance(name=name or f"grid{height}x{width}L{n_labels}", graph=conn, n_labels=n_labels,
                     n_nodes=height * width, height=height, width=width, unary=u, theta=theta,
-                    compat=COMPAT_GENERAL, alpha=alpha, iters=iters)
+                    compat=COMPAT_GENERAL, alpha=float(np.float32(alpha)), iters=iters)
 
 
 def workload_c1():
@@ -180,8 +187,8 @@ def dense_instance(seed, n_nodes=4096, n_labels=21, pos_high=64.0, alpha=0.5, it
     u = _f32(-(logits - lse).T).reshape(1, n_labels, n_nodes)
     feats = _f32(np.concatenate([pos, col], axis=1))
     return Instance(name=name or f"dense{n_nodes}_L{n_labels}", graph=DENSE, n_labels=n_labels,
-                    n_nodes=n_nodes, unary=u, compat=COMPAT_POTTS, potts_w=float(potts_w),
-                    alpha=alpha, iters=iters, features=feats,
+                    n_nodes=n_nodes, unary=u, compat=COMPAT_POTTS, potts_w=float(np.float32(potts_w)),
+                    alpha=float(np.float32(alpha)), iters=iters, features=feats,
                     cooc=cooc if with_cooc else None)
 
 
@@ -231,7 +238,8 @@ def csr_instance(seed, n_nodes, n_labels, avg_degree=6, weighted=True, alpha=0.5
     u = neg_log_softmax_unaries(rng, (n_labels, batch, n_nodes))
     u = np.ascontiguousarray(np.transpose(u, (1, 0, 2)))
     return Instance(name=name or f"csr{n_nodes}_L{n_labels}", graph=CSR, n_labels=n_labels,
-                    n_nodes=n_nodes, unary=u, theta=theta, compat=COMPAT_GENERAL, alpha=alpha,
+                    n_nodes=n_nodes, unary=u, theta=theta, compat=COMPAT_GENERAL,
+                    alpha=float(np.float32(alpha)),
                     iters=iters, row_ptr=row_ptr, col=col, csr_w=w)
 
 

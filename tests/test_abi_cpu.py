@@ -1,0 +1,150 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+rejects invalid descriptors on the host before any launch.  No compute call
+is made (there is no GPU here); fake device addresses are only ever passed to
+host-side validation."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1511_06103_amd import mf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mf.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(mf.LIB_PATH), reason="libmf.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_core_entry_points():
+    names = declared_functions()
+    for core in ("mf_init", "mf_step", "mf_solve", "mf_free_energy", "mf_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(mf.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared set
+    assert sorted(mf.SIGNATURES) == declared_functions()
+
+
+def test_abi_version_and_descriptor_layout():
+    L = mf.lib()
+    assert L.mf_abi_version() == mf.MF_ABI_VERSION
+    assert L.mf_desc_size() == ctypes.sizeof(mf.MFDesc)
+
+
+FAKE = 0x7F0000000000   # never dereferenced: validation is host-only
+
+
+def good_desc(**kw):
+    d = mf.MFDesc()
+    d.abi_version = mf.MF_ABI_VERSION
+    d.batch, d.n_nodes, d.n_labels = 1, 64 * 64, 21
+    d.height, d.width = 64, 64
+    d.graph = mf.GRID8
+    d.compat = mf.COMPAT_GENERAL
+    d.precision = 0
+    d.init = 0
+    d.alpha = 0.5
+    d.unary = FAKE
+    d.theta = FAKE + (1 << 30)
+    d.state = FAKE + (1 << 32)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    ws = mf.lib().mf_workspace_size(ctypes.byref(d))
+    if "workspace" not in kw:
+        d.workspace = FAKE + (1 << 34)
+        d.workspace_bytes = ws
+    return d
+
+
+def validate(d):
+    return mf.lib().mf_validate(ctypes.byref(d))
+
+
+def test_valid_descriptor_passes():
+    assert validate(good_desc()) == mf.MF_OK
+    assert validate(good_desc(compat=mf.COMPAT_POTTS, theta=None, potts_w=1.0)) == mf.MF_OK
+    assert validate(good_desc(alpha=1.0)) == mf.MF_OK           # fully parallel
+    assert validate(good_desc(n_labels=1)) == mf.MF_OK          # trivial but legal
+
+
+@pytest.mark.parametrize("field,value", [
+    ("alpha", 0.0), ("alpha", -0.1), ("alpha", 1.5), ("alpha", float("nan")),
+    ("n_labels", 0), ("batch", 0), ("n_nodes", 0),
+    ("height", 63), ("width", 0),
+    ("graph", 7), ("compat", 5), ("precision", 9), ("init", 3),
+    ("unary", None), ("state", None), ("theta", None),
+    ("abi_version", 99),
+    ("potts_w", float("inf")),
+])
+def test_invalid_descriptor_rejected(field, value):
+    d = good_desc()
+    setattr(d, field, value)
+    st = validate(d)
+    assert st == mf.MF_EINVAL, (field, value, st)
+    assert mf.last_error() != ""
+
+
+def test_misaligned_pointer_rejected():
+    assert validate(good_desc(unary=FAKE + 2)) == mf.MF_EINVAL
+
+
+def test_state_overlapping_unary_rejected():
+    d = good_desc()
+    d.unary = d.state + 4 * 64 * 64 * 21   # inside the second state buffer
+    assert validate(d) == mf.MF_EINVAL
+
+
+def test_too_many_labels_unsupported():
+    assert validate(good_desc(n_labels=mf.MF_MAX_LABELS + 1)) == mf.MF_EUNSUPPORTED
+
+
+def test_workspace_checks():
+    d = good_desc()
+    need = mf.lib().mf_workspace_size(ctypes.byref(d))
+    assert need > 0
+    d.workspace_bytes = need - 1
+    assert validate(d) == mf.MF_ENOWORKSPACE
+    d.workspace_bytes = need
+    d.workspace = None
+    assert validate(d) == mf.MF_ENOWORKSPACE
+    d.workspace = FAKE + 8
+    assert validate(d) == mf.MF_EINVAL       # not 256-byte aligned
+
+
+def test_workspace_size_zero_for_invalid():
+    d = good_desc()
+    d.batch = 0
+    assert mf.lib().mf_workspace_size(ctypes.byref(d)) == 0
+
+
+def test_init_rejects_before_launch():
+    L = mf.lib()
+    h = ctypes.c_void_p(1234)
+    d = good_desc(alpha=2.0)
+    assert L.mf_init(ctypes.byref(d), ctypes.byref(h)) == mf.MF_EINVAL
+    assert not h.value
+    assert "alpha" in mf.last_error()
+    assert L.mf_init(None, ctypes.byref(h)) == mf.MF_EINVAL
+    assert L.mf_step(None, 1) == mf.MF_EINVAL
+    assert L.mf_solve(None, 1, None) == mf.MF_EINVAL
+    assert L.mf_check(None) == mf.MF_EINVAL
+    assert L.mf_current_state(None) is None
+    assert L.mf_iteration(None) == -1
+    L.mf_destroy(None)     # no-op
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    with pytest.raises(ValueError, match="GPU tensor"):
+        mf.MeanField(torch.zeros(1, 2, 9), "grid4", height=3, width=3, potts_w=1.0)
