@@ -176,6 +176,39 @@ void mf_destroy(mf_handle *h);
  * Valid until the next call on the same handle / thread. */
 const char *mf_last_error(const mf_handle *h);
 
+/* Continuous batching: enqueue n_steps >= 0 proximal steps for each of
+ * the count handles hs[0..count) in as few launches as possible (grids
+ * only).  Handles with the same label count, connectivity, compatibility
+ * kind and precision share a launch; each handle keeps its own sizes,
+ * alpha, arrays and iteration counter.  Every handle advances one step per
+ * launch, with the same per-tile arithmetic as mf_step at
+ * steps_per_launch = 1, so its iterates are bitwise those of solving it
+ * alone.  All handles must use the stream of hs[0]; work goes to that
+ * stream.  A handle may appear at most once. */
+mf_status mf_step_many(mf_handle *const *hs, int32_t count, int32_t n_steps);
+
+/* Reverse pass of T unrolled steps on a grid (hand-written adjoint of
+ * Eq. 15 with Eq. 16, differentiated with respect to the unaries and every
+ * entry of Theta as it appears in m = u + Theta S).
+ *
+ * ckpt_states: device [ceil(T / ckpt_every)][B][L][N], log q at t = 0,
+ *   ckpt_every, 2 ckpt_every, ... as produced by the forward steps of h;
+ *   the states between checkpoints are recomputed with one step per launch,
+ *   so the forward must also have run one step per launch
+ *   (steps_per_launch = 1) for the recomputation to reproduce it bitwise.
+ * grad_logq_T: device [B][L][N], dLoss / d log q^T.
+ * grad_unary:  device [B][L][N], overwritten with dLoss / du (including the
+ *   path through log q^0 = -u - lse(-u) when h uses MF_INIT_UNARY).
+ * grad_theta:  device [L][L], overwritten with dLoss / dTheta summed over
+ *   the batch (for POTTS: the gradient with respect to the implied matrix).
+ * work: device scratch of mf_backward_workspace_size bytes, 256-aligned.
+ * Grids only (MF_EUNSUPPORTED otherwise).  Asynchronous on the stream of h;
+ * does not change the state of h. */
+size_t mf_backward_workspace_size(const mf_handle *h, int32_t ckpt_every);
+mf_status mf_backward(mf_handle *h, const float *ckpt_states, int32_t T, int32_t ckpt_every,
+                      const float *grad_logq_T, float *grad_unary, float *grad_theta,
+                      void *work, size_t work_bytes);
+
 /* Build the dense-CRF kernel K_ij = exp(-|f_i - f_j|^2 / 2), K_ii = 0
  * (the Gaussian kernel of the fully connected CRF, Sec. 4.2), rounded to
  * bfloat16 (round to nearest even) into K_bf16 [n][n] (device, uint16 bits).

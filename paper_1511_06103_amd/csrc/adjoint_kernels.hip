@@ -1,0 +1,274 @@
+// Reverse pass of T unrolled proximal steps on a grid (hand-written adjoint).
+//
+// Forward step (Eq. 15 with the fixed step of Eq. 16):
+//   S = A q,  m = u + Theta S,  z = (1 - a) ell - a m,  ell' = z - lse(z)
+// Given g = dLoss/d ell', one reverse step computes
+//   zb   = g - q' (sum_l g_l)                 (through the normalisation)
+//   mb   = -a zb;   ub += mb;   Thetab += sum_i mb_i S_i^T
+//   Sb   = Theta^T mb;   qb = A Sb            (A symmetric on a grid)
+//   g    <- (1 - a) zb + q (.) qb            (dLoss / d ell)
+// Kernel A does everything up to Sb for one 64 x 4 tile (S needs the q halo),
+// kernel B the transposed stencil over Sb (needs the Sb halo) and the new g.
+// Theta_bar partials are per tile: mb and S of the tile's nodes are staged in
+// LDS and the L x L block product is formed there, then reduced over tiles in
+// a fixed order into an FP64 accumulator.
+#include <hip/hip_runtime.h>
+
+#include "mf_internal.h"
+
+namespace mf {
+namespace {
+
+constexpr int AX = kTileX + 2;
+constexpr int AY = kTileY + 2;
+constexpr int AN = AX * AY;
+
+template <int LP, bool EXACT, int CONN, int COMPAT>
+__global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
+  __shared__ float qs[LP * AN];
+  __shared__ float mbs[LP * kThreads];
+  __shared__ float Ss[LP * kThreads];
+  const int L = EXACT ? LP : a.L;
+  const int N = a.N, H = a.H, W = a.W;
+  const int b = blockIdx.z;
+  const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+  const size_t base = (size_t)b * L * N;
+  const int tid = threadIdx.x;
+
+  for (int idx = tid; idx < L * AN; idx += kThreads) {
+    const int l = idx / AN;
+    const int r = idx - l * AN;
+    const int hy = r / AX, hx = r - (r / AX) * AX;
+    const int gy = y0 + hy - 1, gx = x0 + hx - 1;
+    float v = 0.f;
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = __expf(a.ell_t[base + (size_t)l * N + gy * W + gx]);
+    qs[idx] = v;
+  }
+  __syncthreads();
+
+  const int tx = tid % kTileX, ty = tid / kTileX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool inside = x < W && y < H;
+  const int n = inside ? y * W + x : 0;
+  const int p = (ty + 1) * AX + (tx + 1);
+
+  float mb[LP], S[LP];
+#pragma unroll
+  for (int l = 0; l < LP; ++l) {
+    mb[l] = 0.f;
+    S[l] = 0.f;
+  }
+  if (inside) {
+    float g[LP];
+    float sg = 0.f;
+#pragma unroll
+    for (int l = 0; l < LP; ++l) {
+      g[l] = (l < L) ? a.g_in[base + (size_t)l * N + n] : 0.f;
+      sg += g[l];
+    }
+#pragma unroll
+    for (int l = 0; l < LP; ++l) {
+      if (l < L) {
+        const float q1 = __expf(a.ell_t1[base + (size_t)l * N + n]);
+        mb[l] = -a.alpha * (g[l] - q1 * sg);
+        a.u_bar[base + (size_t)l * N + n] += mb[l];
+        const float* q = qs + l * AN + p;
+        float s = q[-AX] + q[-1] + q[1] + q[AX];
+        if (CONN == 8) s += (q[-AX - 1] + q[-AX + 1]) + (q[AX - 1] + q[AX + 1]);
+        S[l] = s;
+      }
+    }
+    // Sb = Theta^T mb
+#pragma unroll
+    for (int k = 0; k < LP; ++k) {
+      if (k < L) {
+        float acc = 0.f;
+        if (COMPAT == MF_COMPAT_POTTS) {
+          float tot = 0.f;
+#pragma unroll
+          for (int l = 0; l < LP; ++l) tot += mb[l];
+          acc = a.potts_w * (tot - mb[k]);
+        } else {
+#pragma unroll
+          for (int l = 0; l < LP; ++l)
+            if (l < L) acc = fmaf(a.theta[l * L + k], mb[l], acc);
+        }
+        a.s_bar[base + (size_t)k * N + n] = acc;
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < LP; ++l) {
+    mbs[l * kThreads + tid] = mb[l];
+    Ss[l * kThreads + tid] = S[l];
+  }
+  __syncthreads();
+  // Theta_bar partial of this tile: P[l][k] = sum_n mb[l][n] S[k][n]
+  const size_t part = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  for (int e = tid; e < L * L; e += kThreads) {
+    const int l = e / L, k = e - (e / L) * L;
+    float acc = 0.f;
+    for (int j = 0; j < kThreads; ++j) acc = fmaf(mbs[l * kThreads + j], Ss[k * kThreads + j], acc);
+    a.theta_part[part * L * L + e] = acc;
+  }
+}
+
+template <int LP, bool EXACT, int CONN>
+__global__ __launch_bounds__(kThreads) void adj_b_kernel(AdjointArgs a) {
+  __shared__ float sb[LP * AN];
+  const int L = EXACT ? LP : a.L;
+  const int N = a.N, H = a.H, W = a.W;
+  const int b = blockIdx.z;
+  const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+  const size_t base = (size_t)b * L * N;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < L * AN; idx += kThreads) {
+    const int l = idx / AN;
+    const int r = idx - l * AN;
+    const int hy = r / AX, hx = r - (r / AX) * AX;
+    const int gy = y0 + hy - 1, gx = x0 + hx - 1;
+    float v = 0.f;
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = a.s_bar[base + (size_t)l * N + gy * W + gx];
+    sb[idx] = v;
+  }
+  __syncthreads();
+  const int tx = tid % kTileX, ty = tid / kTileX;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= W || y >= H) return;
+  const int n = y * W + x;
+  const int p = (ty + 1) * AX + (tx + 1);
+  float g[LP];
+  float sg = 0.f;
+#pragma unroll
+  for (int l = 0; l < LP; ++l) {
+    g[l] = (l < L) ? a.g_in[base + (size_t)l * N + n] : 0.f;
+    sg += g[l];
+  }
+  const float om = 1.f - a.alpha;
+#pragma unroll
+  for (int l = 0; l < LP; ++l) {
+    if (l < L) {
+      const float q1 = __expf(a.ell_t1[base + (size_t)l * N + n]);
+      const float zb = g[l] - q1 * sg;
+      const float* s = sb + l * AN + p;
+      float qb = s[-AX] + s[-1] + s[1] + s[AX];
+      if (CONN == 8) qb += (s[-AX - 1] + s[-AX + 1]) + (s[AX - 1] + s[AX + 1]);
+      const float q0 = __expf(a.ell_t[base + (size_t)l * N + n]);
+      a.g_out[base + (size_t)l * N + n] = om * zb + q0 * qb;
+    }
+  }
+}
+
+// theta_acc[e] += sum over parts of theta_part[part][e], fixed order, FP64.
+__global__ __launch_bounds__(256) void adj_theta_reduce(const float* __restrict__ part, int n_parts, int LL,
+                                                        double* __restrict__ acc) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= LL) return;
+  double s = 0.0;
+  for (int k = 0; k < n_parts; ++k) s += (double)part[(size_t)k * LL + e];
+  acc[e] += s;
+}
+
+// Through the initialisation log q0 = -u - lse(-u): ub += -(g0 - q0 sum g0).
+__global__ __launch_bounds__(256) void adj_init_kernel(const float* __restrict__ g0, const float* __restrict__ ell0,
+                                                       float* __restrict__ u_bar, int L, int N) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  if (n >= N) return;
+  const size_t base = (size_t)b * L * N + n;
+  float sg = 0.f;
+  for (int l = 0; l < L; ++l) sg += g0[base + (size_t)l * N];
+  for (int l = 0; l < L; ++l) {
+    const float q0 = __expf(ell0[base + (size_t)l * N]);
+    u_bar[base + (size_t)l * N] -= g0[base + (size_t)l * N] - q0 * sg;
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_f32(float* __restrict__ p, size_t n, float v) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_f64(double* __restrict__ p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void copy_f32(const float* __restrict__ s, float* __restrict__ d, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+__global__ __launch_bounds__(256) void f64_to_f32(const double* __restrict__ s, float* __restrict__ d, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = (float)s[i];
+}
+
+template <int LP, bool EXACT>
+hipError_t adj_lp(const AdjointArgs& a, int conn, int compat, hipStream_t s) {
+  dim3 grid((a.W + kTileX - 1) / kTileX, (a.H + kTileY - 1) / kTileY, a.B);
+  if (conn == 4) {
+    if (compat == MF_COMPAT_POTTS) hipLaunchKernelGGL((adj_a_kernel<LP, EXACT, 4, MF_COMPAT_POTTS>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((adj_a_kernel<LP, EXACT, 4, MF_COMPAT_GENERAL>), grid, dim3(kThreads), 0, s, a);
+  } else {
+    if (compat == MF_COMPAT_POTTS) hipLaunchKernelGGL((adj_a_kernel<LP, EXACT, 8, MF_COMPAT_POTTS>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((adj_a_kernel<LP, EXACT, 8, MF_COMPAT_GENERAL>), grid, dim3(kThreads), 0, s, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n_parts = (int)(grid.x * grid.y * grid.z);
+  const int LL = a.L * a.L;
+  hipLaunchKernelGGL(adj_theta_reduce, dim3((LL + 255) / 256), dim3(256), 0, s, a.theta_part, n_parts, LL, a.theta_acc);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (conn == 4) hipLaunchKernelGGL((adj_b_kernel<LP, EXACT, 4>), grid, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((adj_b_kernel<LP, EXACT, 8>), grid, dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t adjoint_theta_parts(int B, int H, int W) {
+  return (size_t)B * ((H + kTileY - 1) / kTileY) * ((W + kTileX - 1) / kTileX);
+}
+
+hipError_t launch_adjoint_step(const AdjointArgs& a, int conn, int compat, hipStream_t s) {
+  const int L = a.L;
+  if (L == 2) return adj_lp<2, true>(a, conn, compat, s);
+  if (L == 21) return adj_lp<21, true>(a, conn, compat, s);
+  if (L <= 4) return adj_lp<4, false>(a, conn, compat, s);
+  if (L <= 8) return adj_lp<8, false>(a, conn, compat, s);
+  if (L <= 16) return adj_lp<16, false>(a, conn, compat, s);
+  return adj_lp<32, false>(a, conn, compat, s);
+}
+
+hipError_t launch_adjoint_init(const float* g0, const float* ell0, float* u_bar, int B, int L, int N, hipStream_t s) {
+  hipLaunchKernelGGL(adj_init_kernel, dim3((N + 255) / 256, B), dim3(256), 0, s, g0, ell0, u_bar, L, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(const float* src, float* dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace mf

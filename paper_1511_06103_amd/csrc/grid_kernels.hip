@@ -63,15 +63,16 @@ __device__ inline int halo_lds_pos(int h) {
 // first use (own log q and u of the node, plus this thread's share of the
 // halo), so one memory latency covers the whole tile even at one wavefront
 // per SIMD.
+// The tile body is shared by the single-problem kernel and the many-problem
+// (continuous batching) kernel, so a problem gets bitwise the same iterates
+// whichever kernel advances it.
 template <int LP, bool EXACT, int CONN, int COMPAT, int PREC>
-__global__ __launch_bounds__(kThreads) void grid_step_kernel(StepArgs a, float one_minus_alpha) {
+__device__ inline void grid_step_tile(const StepArgs& a, float one_minus_alpha, int b, int x0, int y0,
+                                      typename MsgT<PREC>::T* __restrict__ qs) {
   using M = MsgT<PREC>;
   constexpr int HREG = (LP * kHalo + kThreads - 1) / kThreads;
-  __shared__ typename M::T qs[LP * HN];
   const int L = EXACT ? LP : a.L;
   const int N = a.N, H = a.H, W = a.W;
-  const int b = blockIdx.z;
-  const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
   const size_t base = (size_t)b * L * N;
   const float* __restrict__ lin = a.state_in + base;
   const int tid = threadIdx.x;
@@ -169,6 +170,32 @@ __global__ __launch_bounds__(kThreads) void grid_step_kernel(StepArgs a, float o
 #pragma unroll
   for (int l = 0; l < LP; ++l)
     if (l < L) out[(size_t)l * N] = z[l] - lse;
+}
+
+template <int LP, bool EXACT, int CONN, int COMPAT, int PREC>
+__global__ __launch_bounds__(kThreads) void grid_step_kernel(StepArgs a, float one_minus_alpha) {
+  __shared__ typename MsgT<PREC>::T qs[LP * HN];
+  grid_step_tile<LP, EXACT, CONN, COMPAT, PREC>(a, one_minus_alpha, blockIdx.z, blockIdx.x * kTileX,
+                                                blockIdx.y * kTileY, qs);
+}
+
+// Many independent problems in one launch: slot k owns workgroups
+// [tile_begin[k], tile_begin[k + 1]); each workgroup runs one tile of its
+// problem.  Every slot shares L, connectivity, compatibility kind and
+// message precision; sizes, alpha and the arrays are per slot.
+template <int LP, bool EXACT, int CONN, int COMPAT, int PREC>
+__global__ __launch_bounds__(kThreads) void grid_step_many_kernel(ManyArgs m) {
+  __shared__ typename MsgT<PREC>::T qs[LP * HN];
+  const int blk = blockIdx.x;
+  int k = 0;
+  while (k + 1 < m.count && blk >= m.tile_begin[k + 1]) ++k;
+  const int t = blk - m.tile_begin[k];
+  const int tiles_x = (m.slot[k].W + kTileX - 1) / kTileX;
+  const int tiles_per_item = tiles_x * ((m.slot[k].H + kTileY - 1) / kTileY);
+  const int b = t / tiles_per_item;
+  const int r = t - b * tiles_per_item;
+  const int ty = r / tiles_x, tx = r - (r / tiles_x) * tiles_x;
+  grid_step_tile<LP, EXACT, CONN, COMPAT, PREC>(m.slot[k], m.one_minus_alpha[k], b, tx * kTileX, ty * kTileY, qs);
 }
 
 // Initial log q per node: -u - lse(-u) (mode 0) or -log L (mode 1); mode 2
@@ -310,7 +337,48 @@ hipError_t step_lp(const StepArgs& a, int conn, int compat, int prec, hipStream_
                                    : step_prec<LP, EXACT, 8, MF_COMPAT_GENERAL>(a, prec, s);
 }
 
+template <int LP, bool EXACT, int CONN, int COMPAT, int PREC>
+hipError_t many_launch(const ManyArgs& m, int total_tiles, hipStream_t s) {
+  hipLaunchKernelGGL((grid_step_many_kernel<LP, EXACT, CONN, COMPAT, PREC>), dim3(total_tiles), dim3(kThreads), 0,
+                     s, m);
+  return hipGetLastError();
+}
+
+template <int LP, bool EXACT, int CONN, int COMPAT>
+hipError_t many_prec(const ManyArgs& m, int total, int prec, hipStream_t s) {
+  switch (prec) {
+    case MF_P_F32: return many_launch<LP, EXACT, CONN, COMPAT, P_F32>(m, total, s);
+    case MF_P_BF16MSG: return many_launch<LP, EXACT, CONN, COMPAT, P_BF16>(m, total, s);
+    default: return many_launch<LP, EXACT, CONN, COMPAT, P_F16>(m, total, s);
+  }
+}
+
+template <int LP, bool EXACT>
+hipError_t many_lp(const ManyArgs& m, int total, int conn, int compat, int prec, hipStream_t s) {
+  if (conn == 4) {
+    return compat == MF_COMPAT_POTTS ? many_prec<LP, EXACT, 4, MF_COMPAT_POTTS>(m, total, prec, s)
+                                     : many_prec<LP, EXACT, 4, MF_COMPAT_GENERAL>(m, total, prec, s);
+  }
+  return compat == MF_COMPAT_POTTS ? many_prec<LP, EXACT, 8, MF_COMPAT_POTTS>(m, total, prec, s)
+                                   : many_prec<LP, EXACT, 8, MF_COMPAT_GENERAL>(m, total, prec, s);
+}
+
 }  // namespace
+
+int grid_tiles(int B, int H, int W) {
+  return B * ((W + kTileX - 1) / kTileX) * ((H + kTileY - 1) / kTileY);
+}
+
+hipError_t launch_grid_step_many(const ManyArgs& m, int L, int conn, int compat, int prec, hipStream_t s) {
+  const int total = m.tile_begin[m.count];
+  if (total <= 0) return hipSuccess;
+  if (L == 2) return many_lp<2, true>(m, total, conn, compat, prec, s);
+  if (L == 21) return many_lp<21, true>(m, total, conn, compat, prec, s);
+  if (L <= 4) return many_lp<4, false>(m, total, conn, compat, prec, s);
+  if (L <= 8) return many_lp<8, false>(m, total, conn, compat, prec, s);
+  if (L <= 16) return many_lp<16, false>(m, total, conn, compat, prec, s);
+  return many_lp<32, false>(m, total, conn, compat, prec, s);
+}
 
 int grid_blocks_per_item(int H, int W) { return (H * W + 255) / 256; }
 
@@ -354,7 +422,11 @@ hipError_t launch_grid_free_energy(const FreeEnergyArgs& a, int conn, int compat
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(a.B), dim3(256), 0, s, a.partials, a.n_blocks, f_out);
+  return launch_reduce_partials(a.partials, a.n_blocks, a.B, f_out, s);
+}
+
+hipError_t launch_reduce_partials(const double* partials, int n_blocks, int B, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(B), dim3(256), 0, s, partials, n_blocks, out);
   return hipGetLastError();
 }
 

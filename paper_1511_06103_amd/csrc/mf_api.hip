@@ -2,11 +2,14 @@
 // workspace layout and kernel dispatch.  No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "mf.h"
 #include "mf_internal.h"
@@ -45,6 +48,27 @@ mf::WorkspaceLayout layout_for(const mf_desc& d) {
   off += align256(sizeof(double) * (size_t)d.batch * (size_t)w.n_blocks);
   w.f_out = off;
   off += align256(sizeof(double) * (size_t)d.batch);
+  if (d.graph == MF_CSR) {
+    w.csr_q = off;
+    off += align256(sizeof(float) * 2 * (size_t)d.batch * (size_t)d.n_nodes *
+                    (size_t)mf::csr_label_stride(d.n_labels));
+  }
+  if (d.graph == MF_DENSE) {
+    const size_t B = (size_t)d.batch;
+    w.dg = mf::dense_geometry(d.n_nodes, d.batch);
+    w.dense_ns = mf::dense_planes(d.precision);
+    const size_t Np = (size_t)w.dg.Np;
+    w.dq = off;
+    off += align256(sizeof(uint16_t) * 2 * B * (size_t)w.dense_ns * 32 * Np);
+    w.ds = off;
+    off += align256(sizeof(float) * B * (size_t)w.dg.KS * Np * 32);
+    w.dt = off;
+    off += align256(sizeof(float) * 2 * B * (size_t)w.dg.NRB * 32);
+    w.dc = off;
+    off += align256(sizeof(int) * B * (size_t)w.dg.NRB);
+    w.dqd = off;
+    off += align256(sizeof(double) * B * (size_t)d.n_nodes * (size_t)d.n_labels);
+  }
   w.total = off;
   return w;
 }
@@ -84,9 +108,18 @@ mf_status check_desc(const mf_desc* d, std::string* msg) {
     *msg = "n_labels above MF_MAX_LABELS";
     return MF_EUNSUPPORTED;
   }
-  if (!is_grid(d->graph)) {
-    *msg = "graph kind not available in this build";
-    return MF_EUNSUPPORTED;
+  if (d->graph == MF_CSR) {
+    if (!d->csr_row_ptr) return bad("csr_row_ptr is NULL");
+    if (d->csr_nnz < 0 || d->csr_nnz > INT32_MAX) return bad("csr_nnz out of range");
+    if (d->csr_nnz > 0 && !d->csr_col) return bad("csr_col is NULL");
+    if (((uintptr_t)d->csr_row_ptr | (uintptr_t)d->csr_col | (uintptr_t)d->csr_w) & 3u)
+      return bad("CSR arrays must be 4-byte aligned");
+  }
+  if (d->graph == MF_DENSE) {
+    if (!d->dense_K) return bad("dense_K is NULL");
+    if ((uintptr_t)d->dense_K & 15u) return bad("dense_K must be 16-byte aligned");
+    if ((uintptr_t)d->cooc & 3u) return bad("cooc must be 4-byte aligned");
+    if ((int64_t)d->n_nodes * d->n_nodes > ((int64_t)1 << 40)) return bad("dense N too large");
   }
   const size_t need = layout_for(*d).total;
   if (!d->workspace || d->workspace_bytes < need) {
@@ -104,12 +137,67 @@ float* buf(const mf_handle* h, int which) {
 
 int* flags_ptr(const mf_handle* h) { return (int*)((char*)h->d.workspace + h->ws.flags); }
 
+char* ws_at(const mf_handle* h, size_t off) { return (char*)h->d.workspace + off; }
+
+mf::DenseStepArgs dense_args(const mf_handle* h, int from) {
+  const mf_desc& d = h->d;
+  const mf::WorkspaceLayout& w = h->ws;
+  const size_t B = (size_t)d.batch, Np = (size_t)w.dg.Np;
+  const size_t plane_elems = B * (size_t)w.dense_ns * 32 * Np;
+  const size_t t_elems = B * (size_t)w.dg.NRB * 32;
+  const size_t elems = B * d.n_labels * d.n_nodes;
+  mf::DenseStepArgs a;
+  a.K = d.dense_K;
+  a.unary = d.unary;
+  a.state_in = d.state + (size_t)from * elems;
+  a.state_out = d.state + (size_t)(from ^ 1) * elems;
+  a.q_in = (const uint16_t*)ws_at(h, w.dq) + (size_t)from * plane_elems;
+  a.q_out = (uint16_t*)ws_at(h, w.dq) + (size_t)(from ^ 1) * plane_elems;
+  a.s_part = (float*)ws_at(h, w.ds);
+  a.t_in = (const float*)ws_at(h, w.dt) + (size_t)from * t_elems;
+  a.t_out = (float*)ws_at(h, w.dt) + (size_t)(from ^ 1) * t_elems;
+  a.counters = (int*)ws_at(h, w.dc);
+  a.theta = d.theta;
+  a.cooc = d.cooc;
+  a.B = d.batch;
+  a.L = d.n_labels;
+  a.N = d.n_nodes;
+  a.Np = w.dg.Np;
+  a.KS = w.dg.KS;
+  a.NRB = w.dg.NRB;
+  a.jchunk = w.dg.jchunk;
+  a.alpha = (float)d.alpha;
+  a.potts_w = d.potts_w;
+  a.inv_n = (float)(1.0 / (double)d.n_nodes);
+  return a;
+}
+
+float* csr_q(const mf_handle* h, int which) {
+  const size_t elems = (size_t)h->d.batch * h->d.n_nodes * mf::csr_label_stride(h->d.n_labels);
+  return (float*)((char*)h->d.workspace + h->ws.csr_q) + (size_t)which * elems;
+}
+
 mf_status enqueue_init(mf_handle* h) {
   const mf_desc& d = h->d;
   hipError_t e = mf::launch_clear_flags(flags_ptr(h), 64, h->stream);
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
+  if (d.graph == MF_CSR) {
+    e = mf::launch_csr_check(d.csr_row_ptr, d.csr_col, d.n_nodes, d.csr_nnz, flags_ptr(h), h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("CSR check launch: ") + hipGetErrorString(e));
+  }
   e = mf::launch_init(d.unary, buf(h, 0), d.batch, d.n_labels, d.n_nodes, d.init, flags_ptr(h), h->stream);
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("init launch: ") + hipGetErrorString(e));
+  if (d.graph == MF_CSR) {
+    e = mf::launch_csr_q_from_state(buf(h, 0), csr_q(h, 0), d.batch, d.n_labels, d.n_nodes, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("CSR q launch: ") + hipGetErrorString(e));
+  }
+  if (d.graph == MF_DENSE) {
+    // planes and column sums of q^0 go to slot 0: prepare writes the "out" side of from = 1
+    mf::DenseStepArgs a = dense_args(h, 1);
+    a.state_in = buf(h, 0);
+    e = mf::launch_dense_prepare(a, h->ws.dense_ns, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("dense prepare launch: ") + hipGetErrorString(e));
+  }
   h->cur = 0;
   h->iter = 0;
   return MF_OK;
@@ -130,8 +218,48 @@ int choose_steps_per_launch(const mf_desc& d) {
   return k < kmax ? k : kmax;
 }
 
+mf_status enqueue_csr_steps(mf_handle* h, int n) {
+  const mf_desc& d = h->d;
+  for (; n > 0; --n) {
+    mf::CsrStepArgs a;
+    a.unary = d.unary;
+    a.state_in = buf(h, h->cur);
+    a.state_out = buf(h, h->cur ^ 1);
+    a.q_in = csr_q(h, h->cur);
+    a.q_out = csr_q(h, h->cur ^ 1);
+    a.row_ptr = d.csr_row_ptr;
+    a.col = d.csr_col;
+    a.w = d.csr_w;
+    a.nnz = d.csr_nnz;
+    a.theta = d.theta;
+    a.B = d.batch;
+    a.L = d.n_labels;
+    a.N = d.n_nodes;
+    a.alpha = (float)d.alpha;
+    a.potts_w = d.potts_w;
+    hipError_t e = mf::launch_csr_step(a, d.compat, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("CSR step launch: ") + hipGetErrorString(e));
+    h->cur ^= 1;
+    h->iter += 1;
+  }
+  return MF_OK;
+}
+
+mf_status enqueue_dense_steps(mf_handle* h, int n) {
+  for (; n > 0; --n) {
+    const mf::DenseStepArgs a = dense_args(h, h->cur);
+    hipError_t e = mf::launch_dense_step(a, h->ws.dense_ns, h->d.compat, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("dense step launch: ") + hipGetErrorString(e));
+    h->cur ^= 1;
+    h->iter += 1;
+  }
+  return MF_OK;
+}
+
 mf_status enqueue_steps(mf_handle* h, int n) {
   const mf_desc& d = h->d;
+  if (d.graph == MF_CSR) return enqueue_csr_steps(h, n);
+  if (d.graph == MF_DENSE) return enqueue_dense_steps(h, n);
   while (n > 0) {
     const int ks = n < h->k_launch ? n : h->k_launch;
     mf::StepArgs a;
@@ -239,7 +367,43 @@ mf_status mf_free_energy(mf_handle* h, double* F_host) {
   a.partials = (double*)((char*)d.workspace + h->ws.partials);
   a.n_blocks = h->ws.n_blocks;
   double* f_dev = (double*)((char*)d.workspace + h->ws.f_out);
-  hipError_t e = mf::launch_grid_free_energy(a, d.graph == MF_GRID4 ? 4 : 8, d.compat, f_dev, h->stream);
+  hipError_t e;
+  if (d.graph == MF_CSR) {
+    mf::CsrFreeEnergyArgs c;
+    c.unary = d.unary;
+    c.state = a.state;
+    c.theta = d.theta;
+    c.row_ptr = d.csr_row_ptr;
+    c.col = d.csr_col;
+    c.w = d.csr_w;
+    c.nnz = d.csr_nnz;
+    c.B = d.batch;
+    c.L = d.n_labels;
+    c.N = d.n_nodes;
+    c.potts_w = d.potts_w;
+    c.partials = a.partials;
+    c.n_blocks = a.n_blocks;
+    e = mf::launch_csr_free_energy(c, d.compat, h->stream);
+    if (e == hipSuccess) e = mf::launch_reduce_partials(c.partials, c.n_blocks, c.B, f_dev, h->stream);
+  } else if (d.graph == MF_DENSE) {
+    mf::DenseFreeEnergyArgs c;
+    c.K = d.dense_K;
+    c.unary = d.unary;
+    c.state = a.state;
+    c.theta = d.theta;
+    c.cooc = d.cooc;
+    c.qd = (double*)ws_at(h, h->ws.dqd);
+    c.B = d.batch;
+    c.L = d.n_labels;
+    c.N = d.n_nodes;
+    c.potts_w = d.potts_w;
+    c.partials = a.partials;
+    c.n_blocks = a.n_blocks;
+    e = mf::launch_dense_free_energy(c, d.compat, h->stream);
+    if (e == hipSuccess) e = mf::launch_reduce_partials(c.partials, c.n_blocks, c.B, f_dev, h->stream);
+  } else {
+    e = mf::launch_grid_free_energy(a, d.graph == MF_GRID4 ? 4 : 8, d.compat, f_dev, h->stream);
+  }
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("free-energy launch: ") + hipGetErrorString(e));
   e = hipMemcpyAsync(F_host, f_dev, sizeof(double) * d.batch, hipMemcpyDeviceToHost, h->stream);
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
@@ -252,6 +416,8 @@ mf_status mf_check(mf_handle* h) {
   hipError_t e = hipMemcpyAsync(&flag, flags_ptr(h), sizeof(int), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("device error: ") + hipGetErrorString(e));
+  if (flag & 2) return fail(h, MF_EINVAL, "malformed CSR arrays (row_ptr not monotone from 0 to nnz, "
+                                         "or a column index out of range)");
   if (flag & 1) return fail(h, MF_ENONFINITE, "non-finite unary or initial state");
   return MF_OK;
 }
@@ -266,9 +432,180 @@ void mf_destroy(mf_handle* h) { delete h; }
 
 const char* mf_last_error(const mf_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
 
+mf_status mf_step_many(mf_handle* const* hs, int32_t count, int32_t n_steps) {
+  if (count < 0 || n_steps < 0) return fail(nullptr, MF_EINVAL, "count and n_steps must be >= 0");
+  if (count == 0 || n_steps == 0) return MF_OK;
+  if (!hs) return fail(nullptr, MF_EINVAL, "hs is NULL");
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i]) return fail(nullptr, MF_EINVAL, "NULL handle in hs");
+    if (!is_grid(hs[i]->d.graph)) return fail(hs[i], MF_EUNSUPPORTED, "mf_step_many batches grid problems");
+    if (hs[i]->stream != hs[0]->stream) return fail(hs[i], MF_EINVAL, "handles use different streams");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(hs[i], MF_EINVAL, "handle listed twice");
+  }
+  const hipStream_t s = hs[0]->stream;
+  std::vector<char> done(count, 0);
+  for (int g = 0; g < count; ++g) {
+    if (done[g]) continue;
+    // the group of handles sharing the kernel instantiation of hs[g]
+    const mf_desc& dg = hs[g]->d;
+    std::vector<mf_handle*> grp;
+    for (int i = g; i < count; ++i) {
+      const mf_desc& di = hs[i]->d;
+      if (!done[i] && di.n_labels == dg.n_labels && di.graph == dg.graph && di.compat == dg.compat &&
+          di.precision == dg.precision) {
+        grp.push_back(hs[i]);
+        done[i] = 1;
+      }
+    }
+    const int conn = dg.graph == MF_GRID4 ? 4 : 8;
+    for (int t = 0; t < n_steps; ++t) {
+      for (size_t c0 = 0; c0 < grp.size(); c0 += mf::kMaxSlots) {
+        const size_t c1 = std::min(grp.size(), c0 + (size_t)mf::kMaxSlots);
+        mf::ManyArgs m;
+        m.count = (int)(c1 - c0);
+        m.tile_begin[0] = 0;
+        for (size_t k = c0; k < c1; ++k) {
+          mf_handle* h = grp[k];
+          const mf_desc& d = h->d;
+          mf::StepArgs& a = m.slot[k - c0];
+          a.unary = d.unary;
+          a.state_in = buf(h, h->cur);
+          a.state_out = buf(h, h->cur ^ 1);
+          a.theta = d.theta;
+          a.B = d.batch;
+          a.L = d.n_labels;
+          a.N = d.n_nodes;
+          a.H = d.height;
+          a.W = d.width;
+          a.alpha = (float)d.alpha;
+          a.potts_w = d.potts_w;
+          m.one_minus_alpha[k - c0] = (float)(1.0 - (double)a.alpha);
+          m.tile_begin[k - c0 + 1] = m.tile_begin[k - c0] + mf::grid_tiles(d.batch, d.height, d.width);
+        }
+        hipError_t e = mf::launch_grid_step_many(m, dg.n_labels, conn, dg.compat, dg.precision, s);
+        if (e != hipSuccess) return fail(grp[c0], MF_EDEVICE, std::string("batched step launch: ") + hipGetErrorString(e));
+        for (size_t k = c0; k < c1; ++k) {
+          grp[k]->cur ^= 1;
+          grp[k]->iter += 1;
+        }
+      }
+    }
+  }
+  return MF_OK;
+}
+
+size_t mf_backward_workspace_size(const mf_handle* h, int32_t ckpt_every) {
+  if (!h || ckpt_every < 1 || !is_grid(h->d.graph)) return 0;
+  const mf_desc& d = h->d;
+  const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
+  const size_t LL = (size_t)d.n_labels * d.n_labels;
+  size_t off = 0;
+  off += align256(sizeof(float) * E * ((size_t)ckpt_every + 1));   // recomputed states
+  off += align256(sizeof(float) * E * 2);                          // gradient ping-pong
+  off += align256(sizeof(float) * E);                              // Theta^T m_bar
+  off += align256(sizeof(float) * LL * mf::adjoint_theta_parts(d.batch, d.height, d.width));
+  off += align256(sizeof(double) * LL);
+  return off;
+}
+
+mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t ckpt_every,
+                      const float* grad_logq_T, float* grad_unary, float* grad_theta, void* work,
+                      size_t work_bytes) {
+  if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
+  const mf_desc& d = h->d;
+  if (!is_grid(d.graph)) return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for grids");
+  if (T < 0 || ckpt_every < 1) return fail(h, MF_EINVAL, "need T >= 0 and ckpt_every >= 1");
+  if (!ckpt_states || !grad_logq_T || !grad_unary || !grad_theta || !work)
+    return fail(h, MF_EINVAL, "NULL argument");
+  if (((uintptr_t)ckpt_states | (uintptr_t)grad_logq_T | (uintptr_t)grad_unary | (uintptr_t)grad_theta) & 3u)
+    return fail(h, MF_EINVAL, "float arrays must be 4-byte aligned");
+  if ((uintptr_t)work & 255u) return fail(h, MF_EINVAL, "work must be 256-byte aligned");
+  if (work_bytes < mf_backward_workspace_size(h, ckpt_every))
+    return fail(h, MF_ENOWORKSPACE, "work smaller than mf_backward_workspace_size");
+  const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
+  const size_t LL = (size_t)d.n_labels * d.n_labels;
+  char* w = (char*)work;
+  float* R = (float*)w;
+  w += align256(sizeof(float) * E * ((size_t)ckpt_every + 1));
+  float* G = (float*)w;
+  w += align256(sizeof(float) * E * 2);
+  float* Sb = (float*)w;
+  w += align256(sizeof(float) * E);
+  float* part = (float*)w;
+  w += align256(sizeof(float) * LL * mf::adjoint_theta_parts(d.batch, d.height, d.width));
+  double* acc = (double*)w;
+  const hipStream_t s = h->stream;
+  const int conn = d.graph == MF_GRID4 ? 4 : 8;
+  auto dev_fail = [&](hipError_t e, const char* what) {
+    return fail(h, MF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e = mf::launch_fill_f32(grad_unary, E, 0.f, s);
+  if (e == hipSuccess) e = mf::launch_fill_f64(acc, LL, s);
+  if (e == hipSuccess) e = mf::launch_copy_f32(grad_logq_T, G, E, s);
+  if (e != hipSuccess) return dev_fail(e, "backward setup");
+  int gc = 0;
+  const int n_seg = (T + ckpt_every - 1) / ckpt_every;
+  for (int seg = n_seg - 1; seg >= 0; --seg) {
+    const int t0 = seg * ckpt_every;
+    const int len = (t0 + ckpt_every < T ? t0 + ckpt_every : T) - t0;
+    e = mf::launch_copy_f32(ckpt_states + (size_t)seg * E, R, E, s);
+    if (e != hipSuccess) return dev_fail(e, "checkpoint copy");
+    for (int k = 1; k <= len; ++k) {
+      mf::StepArgs a;
+      a.unary = d.unary;
+      a.state_in = R + (size_t)(k - 1) * E;
+      a.state_out = R + (size_t)k * E;
+      a.theta = d.theta;
+      a.B = d.batch;
+      a.L = d.n_labels;
+      a.N = d.n_nodes;
+      a.H = d.height;
+      a.W = d.width;
+      a.alpha = (float)d.alpha;
+      a.potts_w = d.potts_w;
+      e = mf::launch_grid_step(a, conn, d.compat, d.precision, s);
+      if (e != hipSuccess) return dev_fail(e, "recompute step");
+    }
+    for (int k = len - 1; k >= 0; --k) {
+      mf::AdjointArgs a;
+      a.g_in = G + (size_t)gc * E;
+      a.g_out = G + (size_t)(gc ^ 1) * E;
+      a.ell_t = R + (size_t)k * E;
+      a.ell_t1 = R + (size_t)(k + 1) * E;
+      a.u_bar = grad_unary;
+      a.s_bar = Sb;
+      a.theta = d.theta;
+      a.theta_part = part;
+      a.theta_acc = acc;
+      a.B = d.batch;
+      a.L = d.n_labels;
+      a.N = d.n_nodes;
+      a.H = d.height;
+      a.W = d.width;
+      a.alpha = (float)d.alpha;
+      a.potts_w = d.potts_w;
+      e = mf::launch_adjoint_step(a, conn, d.compat, s);
+      if (e != hipSuccess) return dev_fail(e, "adjoint step");
+      gc ^= 1;
+    }
+  }
+  if (d.init == MF_INIT_UNARY) {
+    e = mf::launch_adjoint_init(G + (size_t)gc * E, ckpt_states, grad_unary, d.batch, d.n_labels, d.n_nodes, s);
+    if (e != hipSuccess) return dev_fail(e, "init adjoint");
+  }
+  e = mf::launch_f64_to_f32(acc, grad_theta, LL, s);
+  if (e != hipSuccess) return dev_fail(e, "theta gradient");
+  return MF_OK;
+}
+
 mf_status mf_dense_kernel(const float* features, int32_t n, int32_t dim, uint16_t* K_bf16, void* stream) {
-  (void)features; (void)n; (void)dim; (void)K_bf16; (void)stream;
-  return fail(nullptr, MF_EUNSUPPORTED, "dense kernel builder not available in this build");
+  if (!features || !K_bf16) return fail(nullptr, MF_EINVAL, "features or K is NULL");
+  if (n < 1 || dim < 1 || dim > 16) return fail(nullptr, MF_EINVAL, "need n >= 1 and 1 <= dim <= 16");
+  if (((uintptr_t)features & 3u) || ((uintptr_t)K_bf16 & 1u)) return fail(nullptr, MF_EINVAL, "misaligned pointer");
+  hipError_t e = mf::launch_dense_kernel(features, n, dim, K_bf16, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, MF_EDEVICE, std::string("dense kernel launch: ") + hipGetErrorString(e));
+  return MF_OK;
 }
 
 }  // extern "C"

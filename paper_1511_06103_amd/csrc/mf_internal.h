@@ -26,6 +26,15 @@ struct StepArgs {
   float potts_w;
 };
 
+// Continuous batching: up to kMaxSlots problems advanced by one launch.
+constexpr int kMaxSlots = 48;
+struct ManyArgs {
+  StepArgs slot[kMaxSlots];
+  float one_minus_alpha[kMaxSlots];
+  int tile_begin[kMaxSlots + 1];
+  int count;
+};
+
 struct FreeEnergyArgs {
   const float* unary;
   const float* state;
@@ -36,11 +45,97 @@ struct FreeEnergyArgs {
   int n_blocks;            // workgroups per batch item
 };
 
+struct CsrStepArgs {
+  const float* unary;      // [B][L][N]
+  const float* state_in;   // [B][L][N]
+  float* state_out;        // [B][L][N]
+  const float* q_in;       // [B][N][LQ] node-major q of state_in
+  float* q_out;            // [B][N][LQ] node-major q of state_out
+  const int* row_ptr;      // [N + 1]
+  const int* col;          // [nnz]
+  const float* w;          // [nnz] or nullptr
+  long long nnz;
+  const float* theta;
+  int B, L, N;
+  float alpha;
+  float potts_w;
+};
+
+struct CsrFreeEnergyArgs {
+  const float* unary;
+  const float* state;
+  const float* theta;
+  const int* row_ptr;
+  const int* col;
+  const float* w;
+  long long nnz;
+  int B, L, N;
+  float potts_w;
+  double* partials;
+  int n_blocks;
+};
+
+struct DenseStepArgs {
+  const uint16_t* K;       // [N][N] bf16 bits
+  const float* unary;      // [B][L][N]
+  const float* state_in;   // [B][L][N]
+  float* state_out;
+  const uint16_t* q_in;    // [B][NS][32][Np] bf16 planes of q(state_in)
+  uint16_t* q_out;         // planes of q(state_out)
+  float* s_part;           // [B][KS][Np][32] partial S
+  const float* t_in;       // [B][NRB][32] column sums of q(state_in) per row block
+  float* t_out;
+  int* counters;           // [B][NRB] slice arrival counters (zero between launches)
+  const float* theta;      // [L][L] (general)
+  const float* cooc;       // [L][L] or nullptr
+  int B, L, N, Np, KS, NRB, jchunk;
+  float alpha, potts_w, inv_n;
+};
+
+struct DenseGeometry {
+  int Np = 0, NRB = 0, KS = 0, jchunk = 0;
+};
+
+struct DenseFreeEnergyArgs {
+  const uint16_t* K;
+  const float* unary;
+  const float* state;
+  const float* theta;
+  const float* cooc;
+  double* qd;              // [B][N][L] scratch
+  int B, L, N;
+  float potts_w;
+  double* partials;
+  int n_blocks;
+};
+
+struct AdjointArgs {
+  const float* g_in;       // [B][L][N] dLoss / d ell^{t+1}
+  float* g_out;            // [B][L][N] dLoss / d ell^t
+  const float* ell_t;      // [B][L][N]
+  const float* ell_t1;     // [B][L][N]
+  float* u_bar;            // [B][L][N] accumulated
+  float* s_bar;            // [B][L][N] scratch: Theta^T m_bar
+  const float* theta;
+  float* theta_part;       // [parts][L][L]
+  double* theta_acc;       // [L][L] accumulated
+  int B, L, N, H, W;
+  float alpha, potts_w;
+};
+
 // Workspace layout (offsets in bytes from the 256-aligned workspace start).
 struct WorkspaceLayout {
-  size_t flags = 0;        // int32[64]: [0] non-finite input seen
+  size_t flags = 0;        // int32[64]: [0] bit 0 non-finite input, bit 1 malformed CSR
   size_t partials = 0;     // double[B][n_blocks]
   size_t f_out = 0;        // double[B]
+  size_t csr_q = 0;        // float[2][B][N][LQ] (CSR only)
+  size_t dq = 0;           // uint16[2][B][NS][32][Np] q planes (dense only)
+  size_t ds = 0;           // float[B][KS][Np][32] partial S
+  size_t dt = 0;           // float[2][B][NRB][32] column sums
+  size_t dc = 0;           // int[B][NRB] counters
+  size_t dqd = 0;          // double[B][N][L] free-energy scratch
+  DenseGeometry dg;
+  int dense_ns = 0;
   size_t total = 0;
   int n_blocks = 0;
 };
@@ -58,6 +153,32 @@ hipError_t launch_grid_free_energy(const FreeEnergyArgs& a, int conn, int compat
 hipError_t launch_clear_flags(int* flags, int n, hipStream_t s);
 hipError_t launch_exp(const float* state, float* q, size_t count, hipStream_t s);
 hipError_t launch_dense_kernel(const float* f, int n, int dim, uint16_t* K, hipStream_t s);
+int dense_planes(int precision);
+DenseGeometry dense_geometry(int N, int B);
+hipError_t launch_dense_prepare(const DenseStepArgs& a, int NS, hipStream_t s);
+hipError_t launch_dense_step(const DenseStepArgs& a, int NS, int compat, hipStream_t s);
+hipError_t launch_dense_free_energy(const DenseFreeEnergyArgs& a, int compat, hipStream_t s);
+
+hipError_t launch_reduce_partials(const double* partials, int n_blocks, int B, double* out, hipStream_t s);
+
+int csr_label_stride(int L);
+hipError_t launch_csr_check(const int* row_ptr, const int* col, int N, long long nnz, int* flags,
+                            hipStream_t s);
+hipError_t launch_csr_q_from_state(const float* state, float* qn, int B, int L, int N, hipStream_t s);
+hipError_t launch_csr_step(const CsrStepArgs& a, int compat, hipStream_t s);
+hipError_t launch_csr_free_energy(const CsrFreeEnergyArgs& a, int compat, hipStream_t s);
+
+size_t adjoint_theta_parts(int B, int H, int W);
+hipError_t launch_adjoint_step(const AdjointArgs& a, int conn, int compat, hipStream_t s);
+hipError_t launch_adjoint_init(const float* g0, const float* ell0, float* u_bar, int B, int L, int N,
+                               hipStream_t s);
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, size_t n, hipStream_t s);
+hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t s);
+
+int grid_tiles(int B, int H, int W);
+hipError_t launch_grid_step_many(const ManyArgs& m, int L, int conn, int compat, int prec, hipStream_t s);
 
 int grid_blocks_per_item(int H, int W);
 

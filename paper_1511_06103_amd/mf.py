@@ -70,6 +70,11 @@ SIGNATURES = {
     "mf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "mf_dense_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "mf_step_many": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32]),
+    "mf_backward_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int32]),
+    "mf_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t]),
 }
 
 _lib = None
@@ -130,6 +135,17 @@ def dense_kernel(features: torch.Tensor, stream=None) -> torch.Tensor:
     s = torch.cuda.current_stream(f.device).cuda_stream if stream is None else stream
     _check(lib().mf_dense_kernel(_ptr(f), n, dim, _ptr(K), ctypes.c_void_p(s)))
     return K
+
+
+def step_many(solvers, n_steps: int = 1):
+    """Advance every solver by n_steps in shared launches (continuous batching)."""
+    solvers = list(solvers)
+    if not solvers:
+        return
+    arr = (ctypes.c_void_p * len(solvers))(*[s._h().value for s in solvers])
+    st = lib().mf_step_many(arr, len(solvers), int(n_steps))
+    if st != MF_OK:
+        raise MFError(st, last_error())
 
 
 class MeanField:
@@ -229,6 +245,27 @@ class MeanField:
         out = (ctypes.c_double * self.shape[0])()
         _check(lib().mf_free_energy(self._h(), out), self._handle)
         return np.array(out[:], dtype=np.float64)
+
+    def backward(self, ckpt_states: torch.Tensor, iters: int, ckpt_every: int, grad_logq_T: torch.Tensor):
+        """Reverse pass of ``iters`` steps: returns (dLoss/du [B, L, N], dLoss/dTheta [L, L])."""
+        B, L, N = self.shape
+        n_ckpt = (iters + ckpt_every - 1) // ckpt_every
+        _dev_tensor(ckpt_states, torch.float32, "ckpt_states", self.device)
+        _dev_tensor(grad_logq_T, torch.float32, "grad_logq_T", self.device)
+        if ckpt_states.shape[0] < n_ckpt or tuple(ckpt_states.shape[1:]) != self.shape:
+            raise ValueError("ckpt_states must be [ceil(iters / ckpt_every), B, L, N]")
+        if tuple(grad_logq_T.shape) != self.shape:
+            raise ValueError("grad_logq_T must be [B, L, N]")
+        nbytes = lib().mf_backward_workspace_size(self._h(), int(ckpt_every))
+        if nbytes == 0:
+            _check(MF_EUNSUPPORTED if self.desc.graph not in (GRID4, GRID8) else MF_EINVAL, self._handle)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        gu = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        gt = torch.empty((L, L), dtype=torch.float32, device=self.device)
+        _check(lib().mf_backward(self._h(), _ptr(ckpt_states), int(iters), int(ckpt_every), _ptr(grad_logq_T),
+                                 _ptr(gu), _ptr(gt), _ptr(work), nbytes), self._handle)
+        self._bwd_work = work    # keep alive until the stream has consumed it
+        return gu, gt
 
     def check(self):
         _check(lib().mf_check(self._h()), self._handle)

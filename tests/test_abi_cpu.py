@@ -148,3 +148,28 @@ def test_binding_refuses_cpu_tensors():
     import torch
     with pytest.raises(ValueError, match="GPU tensor"):
         mf.MeanField(torch.zeros(1, 2, 9), "grid4", height=3, width=3, potts_w=1.0)
+
+
+def csr_desc(**kw):
+    base = dict(graph=mf.CSR, height=0, width=0, csr_row_ptr=FAKE + (1 << 36), csr_col=FAKE + (1 << 37),
+                csr_nnz=1000)
+    base.update(kw)
+    return good_desc(**base)
+
+
+def test_csr_descriptor_validation():
+    assert validate(csr_desc()) == mf.MF_OK
+    assert validate(csr_desc(csr_w=FAKE + (1 << 38))) == mf.MF_OK
+    assert validate(csr_desc(csr_nnz=0, csr_col=None)) == mf.MF_OK      # no edges
+    assert validate(csr_desc(csr_row_ptr=None)) == mf.MF_EINVAL
+    assert validate(csr_desc(csr_col=None)) == mf.MF_EINVAL
+    assert validate(csr_desc(csr_nnz=-1)) == mf.MF_EINVAL
+    assert validate(csr_desc(csr_nnz=1 << 33)) == mf.MF_EINVAL
+    assert validate(csr_desc(csr_col=FAKE + (1 << 37) + 2)) == mf.MF_EINVAL
+
+
+def test_csr_workspace_holds_node_major_q():
+    g = mf.lib().mf_workspace_size(ctypes.byref(good_desc()))
+    c = mf.lib().mf_workspace_size(ctypes.byref(csr_desc()))
+    # two node-major copies of q, L = 21 padded to 24
+    assert c - g >= 2 * 64 * 64 * 24 * 4

@@ -1,0 +1,128 @@
+"""GPU parity of the general-graph (CSR gather) path against the FP64 oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import cases  # noqa: E402
+import oracle as O  # noqa: E402
+from paper_1511_06103_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu_state(s):
+    torch.cuda.synchronize()
+    return s.current_state().detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("n,L,deg,weighted,B", [
+    (1, 2, 0, False, 1),
+    (300, 2, 4, True, 1),
+    (1000, 3, 6, False, 2),
+    (2000, 21, 8, True, 1),
+    (777, 32, 5, True, 1),
+    (4096, 13, 12, False, 1),
+])
+def test_csr_end_to_end(n, L, deg, weighted, B):
+    inst = synth.csr_instance(40 + n + L, n, L, deg, weighted, alpha=0.5, iters=10, batch=B)
+    s = cases.gpu_solver(inst)
+    g0 = gpu_state(s)
+    for b in range(B):
+        np.testing.assert_allclose(np.exp(g0[b]), np.exp(O.init_state(inst.unary[b].astype(np.float64))),
+                                   atol=1e-6)
+    s.step(10)
+    g = gpu_state(s)
+    for b in range(B):
+        ref = O.solve(cases.oracle_model(inst, b), 0.5, 10)[-1]
+        assert cases.max_dq(g[b], ref) <= 1e-5
+    s.check()
+
+
+def test_csr_one_step_from_identical_state():
+    inst = synth.csr_instance(5, 5000, 21, 8, True)
+    model = cases.oracle_model(inst)
+    start = O.solve(model, 0.5, 7)[-1].astype(np.float32)
+    B, L, N = inst.unary.shape
+    st = torch.empty((2, B, L, N), dtype=torch.float32, device="cuda:0")
+    st[0].copy_(torch.from_numpy(start[None]))
+    s = cases.gpu_solver(inst, init="state", state=st)
+    s.step(1)
+    ref = O.prox_step(start.astype(np.float64), model, 0.5)
+    assert cases.max_dq(gpu_state(s)[0], ref) <= 1e-6
+
+
+def test_csr_of_a_grid_matches_grid_path():
+    ginst = synth.grid_theta_random(8, 40, 33, 5, synth.GRID8, iters=8)
+    edges = O.grid_edges(40, 33, 8)
+    N = 40 * 33
+    rows = [[] for _ in range(N)]
+    for a, b in edges:
+        rows[a].append(b)
+        rows[b].append(a)
+    row_ptr = np.cumsum([0] + [len(r) for r in rows]).astype(np.int32)
+    col = np.concatenate([sorted(r) for r in rows]).astype(np.int32)
+    cinst = synth.Instance(name="grid-as-csr", graph=synth.CSR, n_labels=5, n_nodes=N, unary=ginst.unary,
+                           theta=ginst.theta, alpha=ginst.alpha, iters=8, row_ptr=row_ptr, col=col)
+    a = cases.gpu_solver(ginst)
+    c = cases.gpu_solver(cinst)
+    a.step(8)
+    c.step(8)
+    assert cases.max_dq(gpu_state(a), gpu_state(c)) <= 2e-6
+
+
+def test_csr_potts_and_free_energy():
+    base = synth.csr_instance(77, 1500, 4, 6, True)
+    inst = synth.Instance(name="csr-potts", graph=synth.CSR, n_labels=4, n_nodes=1500, unary=base.unary,
+                          compat=synth.COMPAT_POTTS, potts_w=0.75, alpha=0.5, iters=6,
+                          row_ptr=base.row_ptr, col=base.col, csr_w=base.csr_w)
+    for which in (inst, base):
+        s = cases.gpu_solver(which)
+        s.step(6)
+        g = gpu_state(s)
+        model = cases.oracle_model(which)
+        assert cases.max_dq(g[0], O.solve(model, which.alpha, 6)[-1]) <= 1e-5
+        F = s.free_energy()[0]
+        ref = O.free_energy(g[0], model)
+        assert abs(F - ref) <= 1e-10 * max(1.0, abs(ref))
+
+
+def test_csr_without_edges_is_the_unary_closed_form():
+    u = synth.grid_potts_normal(3, 1, 3, width=500).unary
+    inst = synth.Instance(name="empty", graph=synth.CSR, n_labels=3, n_nodes=500, unary=u,
+                          theta=np.ones((3, 3), np.float32), alpha=0.5, iters=5,
+                          row_ptr=np.zeros(501, np.int32), col=np.zeros(0, np.int32))
+    s = cases.gpu_solver(inst, init="uniform")
+    s.step(5)
+    ell0 = O.init_state(u[0].astype(np.float64), 1)
+    c = 0.5 ** 5
+    ref = O.normalise(c * ell0 - (1 - c) * u[0].astype(np.float64))
+    assert cases.max_dq(gpu_state(s)[0], ref) <= 1e-6
+
+
+@pytest.mark.parametrize("defect", ["col_out_of_range", "row_ptr_decreasing", "row_ptr_end"])
+def test_malformed_csr_reported_without_fault(defect):
+    from paper_1511_06103_amd import mf
+    inst = synth.csr_instance(9, 200, 3, 4, False)
+    row_ptr, col = inst.row_ptr.copy(), inst.col.copy()
+    if defect == "col_out_of_range":
+        col[5] = 200 + 7
+    elif defect == "row_ptr_decreasing":
+        row_ptr[50] = row_ptr[49] - 1 if row_ptr[49] > 0 else row_ptr[51] + 1
+    else:
+        row_ptr[-1] = row_ptr[-1] - 1
+    inst.row_ptr, inst.col = row_ptr, col
+    s = cases.gpu_solver(inst)
+    s.step(2)                       # runs with clamped accesses
+    with pytest.raises(mf.MFError) as e:
+        s.check()
+    assert e.value.status == mf.MF_EINVAL
