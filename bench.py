@@ -11,9 +11,10 @@ workload is the 256 x 256, 8-connected, L = 21 grid with a random symmetric
 Theta, alpha = 0.5 and T = 100 iterations (FP32).
 
 Prints one JSON line: node-label updates/s = B * N * L * T * K / time, with
-p50/p99 solve latency, the roofline of the dominant kernel (the grid step,
-timed per launch with HIP events on the stream it runs on) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+p50/p99 solve latency, the roofline of the dominant kernel (the step kernel
+as the solve launches it, K fused steps per launch, timed per launch with HIP
+events on the stream it runs on) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
 
 Profiling helpers (single GPU):
     --mode kernel   only the dominant kernel, --launches times (for counters)
@@ -37,7 +38,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_UPDATE = 12          # read log q (4) + read u (4) + write log q' (4)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_step_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1511_06103_amd", "csrc", "grid_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_06103_amd", "csrc", f)
+                  for f in ("grid_temporal.h", "grid_lanes.h", "msg_codec.h")]
 
 WORKLOADS = {
     "grid256_L21_theta": lambda s: s.workload_c2(),
@@ -52,8 +54,11 @@ def log(*a):
 
 
 def source_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def make_solver(inst, torch, mf):
@@ -69,17 +74,20 @@ def make_solver(inst, torch, mf):
 
 
 def time_step_launches(solver, torch, launches):
-    """Average duration of one grid-step launch, HIP events around each launch."""
+    """Average duration of one launch of the step kernel as the solve runs it:
+    each mf_step(K) with K = steps fused per launch is exactly one launch.
+    HIP events are recorded around each launch on the solver's stream."""
     stream = solver.stream
+    k = solver.steps_per_launch
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
     with torch.cuda.stream(stream):
         for a, b in ev:
             a.record(stream)
-            solver.step(1)
+            solver.step(k)
             b.record(stream)
     torch.cuda.synchronize()
     d = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
-    return float(d.mean()), float(np.median(d))
+    return float(d.mean()), float(np.median(d)), k
 
 
 def cpu_baseline(inst, budget_s=12.0):
@@ -107,13 +115,15 @@ def cpu_baseline(inst, budget_s=12.0):
                       f"({el:.1f} s, 1 thread)"}
 
 
-def load_traffic(algo_bytes_per_launch):
+def load_traffic(k):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/), or
+    None when the kernel sources changed since they were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != source_hash():
+    if t.get("kernel_source_sha256_16") != source_hash() or t.get("steps_per_launch") != k:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -160,10 +170,11 @@ def main():
 
     if args.mode == "kernel":
         solver.solve(0)
+        k = solver.steps_per_launch
         for i in range(args.launches):
-            solver.step(1)
+            solver.step(k)
         torch.cuda.synchronize()
-        log(f"kernel mode: {args.launches} step launches done")
+        log(f"kernel mode: {args.launches} launches of {k} steps done")
         return
 
     for i in range(args.warmup):
@@ -187,16 +198,17 @@ def main():
     value = updates / total
     log(f"timed {args.steps} solves: wall {wall * 1e3:.3f} ms, HIP events {ev_total * 1e3:.3f} ms")
 
-    # dominant kernel: one grid-step launch over all B * N * L node-labels
-    mean_d, med_d = time_step_launches(solver, torch, args.launches)
-    algo = BYTES_PER_UPDATE * B * N * L
+    # dominant kernel: one step-kernel launch = K steps over all B * N * L node-labels
+    mean_d, med_d, k = time_step_launches(solver, torch, args.launches)
+    algo = BYTES_PER_UPDATE * B * N * L * k
     achieved = algo / mean_d / 1e9
-    traffic = load_traffic(algo)
+    traffic = load_traffic(k)
+    kname = "mf::temporal::multi_step_kernel" if k > 1 else "mf::lanes::step_kernel"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "grid_step_kernel", "launch_us_mean": round(mean_d * 1e6, 3),
+                "kernel": kname, "steps_per_launch": k, "launch_us_mean": round(mean_d * 1e6, 3),
                 "launch_us_median": round(med_d * 1e6, 3), "algorithmic_bytes_per_launch": algo}
-    log(f"grid step: {mean_d * 1e6:.2f} us mean, {med_d * 1e6:.2f} us median per launch -> {achieved:.0f} GB/s")
+    log(f"{kname} (K={k}): {mean_d * 1e6:.2f} us mean, {med_d * 1e6:.2f} us median per launch -> {achieved:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu:

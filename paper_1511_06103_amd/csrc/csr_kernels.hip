@@ -173,7 +173,8 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
     const size_t base = (size_t)b * L * N;
     const float* st = a.state + base;
     double S[MF_MAX_LABELS];
-    for (int l = 0; l < L; ++l) S[l] = 0.0;
+#pragma unroll
+    for (int l = 0; l < MF_MAX_LABELS; ++l) S[l] = 0.0;
     long long e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
     e0 = e0 < 0 ? 0 : e0;
     e1 = e1 > a.nnz ? a.nnz : e1;
@@ -181,11 +182,16 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
       const int j = a.col[e];
       if (j < 0 || j >= N) continue;
       const double w = a.w ? (double)a.w[e] : 1.0;
-      for (int l = 0; l < L; ++l) S[l] += w * exp((double)st[(size_t)l * N + j]);
+#pragma unroll
+      for (int l = 0; l < MF_MAX_LABELS; ++l)
+        if (l < L) S[l] += w * exp((double)st[(size_t)l * N + j]);
     }
     double tot = 0.0;
-    for (int l = 0; l < L; ++l) tot += S[l];
-    for (int l = 0; l < L; ++l) {
+#pragma unroll
+    for (int l = 0; l < MF_MAX_LABELS; ++l) tot += S[l];
+#pragma unroll
+    for (int l = 0; l < MF_MAX_LABELS; ++l) {
+      if (l >= L) continue;
       const double lq = (double)st[(size_t)l * N + i];
       const double q = exp(lq);
       double pm;
@@ -193,7 +199,9 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
         pm = (double)a.potts_w * (tot - S[l]);
       } else {
         pm = 0.0;
-        for (int k = 0; k < L; ++k) pm += (double)a.theta[l * L + k] * S[k];
+#pragma unroll
+        for (int k = 0; k < MF_MAX_LABELS; ++k)
+          if (k < L) pm += (double)a.theta[l * L + k] * S[k];
       }
       f += q * ((double)a.unary[base + (size_t)l * N + i] + lq + 0.5 * pm);
     }

@@ -1,0 +1,355 @@
+// One proximal step on a grid with LPN lanes per node (label-parallel).
+//
+// Each node's labels are split over a group of LPN adjacent lanes, LG labels
+// per lane (LP = LG * LPN >= L slots).  A lane stages q for its own labels,
+// sums the neighbours for them, then receives the other lanes' neighbour
+// sums through quad-permute DPP broadcasts so that it can form its LG rows
+// of Theta S; the per-node log-sum-exp is a max and a sum reduced across
+// the LPN lanes with DPP butterflies.  Splitting a node over lanes
+// multiplies the wavefront count by LPN: a 256 x 256 grid then keeps
+// several wavefronts per SIMD instead of one, so memory and LDS latency are
+// covered by other wavefronts instead of stalling the only one.
+//
+// Step (Eq. 15 with the fixed step of Eq. 16), per node i:
+//   S_i = sum of q_j over the 4/8 grid neighbours (free boundary)
+//   m_i = u_i + Theta S_i          (Potts: w (sum(S_i) 1 - S_i))
+//   z_i = (1 - alpha) log q_i - alpha m_i;   log q_i <- z_i - lse(z_i)
+//
+// The tile body is shared by the single-problem kernel and the
+// many-problem (continuous batching) kernel, so a problem gets bitwise the
+// same iterates whichever of the two advances it.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mf_internal.h"
+#include "msg_codec.h"
+
+namespace mf {
+namespace lanes {
+
+// Quad-permute DPP: lane i of every group of four reads lane ((CTRL >> 2i) & 3).
+template <int CTRL>
+__device__ inline float qperm(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Value of lane S of this node's group of LPN lanes.
+template <int LPN, int S>
+__device__ inline float group_bcast(float v) {
+  if constexpr (LPN == 1) {
+    return v;
+  } else if constexpr (LPN == 2) {
+    return qperm<S | (S << 2) | ((2 + S) << 4) | ((2 + S) << 6)>(v);
+  } else {
+    return qperm<S | (S << 2) | (S << 4) | (S << 6)>(v);
+  }
+}
+
+template <int LPN>
+__device__ inline float group_max(float v) {
+  if constexpr (LPN >= 2) v = fmaxf(v, qperm<0xB1>(v));   // xor 1
+  if constexpr (LPN >= 4) v = fmaxf(v, qperm<0x4E>(v));   // xor 2
+  return v;
+}
+
+template <int LPN>
+__device__ inline float group_sum(float v) {
+  if constexpr (LPN >= 2) v += qperm<0xB1>(v);
+  if constexpr (LPN >= 4) v += qperm<0x4E>(v);
+  return v;
+}
+
+// Plane stride of the q tile in LDS: at least HN, chosen so that the LPN
+// lanes of a node (reading LPN different label planes at the same position)
+// fall into different LDS banks.
+template <int LG, int LPN>
+constexpr int plane_stride(int hn) {
+  if (LPN == 1) return hn;
+  const int want = 64 / LPN;                      // bank offset between sub-lanes
+  for (int ps = hn; ps < hn + 64; ++ps)
+    if ((LG * ps) % 64 == want) return ps;
+  return hn;
+}
+
+template <int LG, int LPN, int TX, int TY>
+struct Geometry {
+  static constexpr int NT = TX * TY * LPN;           // threads per workgroup
+  static constexpr int LP = LG * LPN;                // label slots
+  static constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+  static constexpr int PS = plane_stride<LG, LPN>(HN);
+  static constexpr int LS = (LP + 3) & ~3;           // Theta row stride in LDS
+  static constexpr int HALO = 2 * HX + 2 * TY;       // halo ring nodes
+};
+
+template <int TX, int TY>
+__device__ inline int halo_pos(int h) {
+  constexpr int HX = TX + 2, HY = TY + 2;
+  if (h < HX) return h;                                   // top row
+  if (h < 2 * HX) return (HY - 1) * HX + (h - HX);        // bottom row
+  const int k = h - 2 * HX;                               // sides, rows 1..TY
+  return (1 + (k >> 1)) * HX + ((k & 1) ? HX - 1 : 0);
+}
+
+template <int LG, int LPN, int TX, int TY, int PREC>
+struct Smem {
+  using G = Geometry<LG, LPN, TX, TY>;
+  typename MsgT<PREC>::T q[G::LP * G::PS];
+  float theta[G::LP * G::LS];
+};
+
+// Branch-free tile body.  LC is the label count when it is known at compile
+// time (0: runtime a.L); slots l >= L are carried with q = 0 and a zero row
+// and column of Theta, so every lane runs the same straight-line code and
+// only the final store is masked.
+template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY>
+__device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b, int x0, int y0,
+                                 Smem<LG, LPN, TX, TY, PREC>& sm) {
+  using G = Geometry<LG, LPN, TX, TY>;
+  using M = MsgT<PREC>;
+  constexpr int LP = G::LP, PS = G::PS, LS = G::LS, HX = G::HX, NT = G::NT, HALO = G::HALO;
+  constexpr int HREG = (LP * HALO + NT - 1) / NT;
+  constexpr int TREG = (COMPAT == MF_COMPAT_GENERAL) ? (LP * LS + NT - 1) / NT : 0;
+  constexpr int KMAX = LC > 0 ? LC : LP;      // Theta columns that can be nonzero
+  const int L = LC > 0 ? LC : a.L;
+  const unsigned N = (unsigned)a.N;
+  const int H = a.H, W = a.W;
+  const size_t base = (size_t)b * L * N;
+  const float* __restrict__ lin = a.state_in + base;
+  const float* __restrict__ ug = a.unary + base;
+  const int tid = threadIdx.x;
+  const int sub = tid % LPN, nl = tid / LPN;
+  const int tx = nl % TX, ty = nl / TX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool inside = x < W && y < H;
+  const unsigned n = inside ? (unsigned)(y * W + x) : 0u;
+
+  // All global loads first: own labels, this thread's share of the halo, Theta.
+  // Addresses are clamped into range and the value is selected afterwards, so
+  // no load is skipped by a branch.
+  bool valid[LG];
+  float ell[LG], uu[LG];
+#pragma unroll
+  for (int j = 0; j < LG; ++j) {
+    const int l = sub * LG + j;
+    valid[j] = l < L;
+    const unsigned lc = (unsigned)(l < L ? l : L - 1);
+    ell[j] = lin[lc * N + n];
+    uu[j] = ug[lc * N + n];
+  }
+  float hv[HREG];
+#pragma unroll
+  for (int r = 0; r < HREG; ++r) {
+    const int f = tid + r * NT;
+    const int l = f / HALO;
+    const int pos = halo_pos<TX, TY>(f - l * HALO);
+    const int hy = pos / HX, hx = pos - (pos / HX) * HX;
+    const int gy = y0 + hy - 1, gx = x0 + hx - 1;
+    const bool ok = f < LP * HALO && l < L && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    const unsigned off = ok ? (unsigned)l * N + (unsigned)(gy * W + gx) : 0u;
+    const float v = lin[off];
+    hv[r] = ok ? v : -INFINITY;
+  }
+  float tv[TREG > 0 ? TREG : 1];
+#pragma unroll
+  for (int r = 0; r < TREG; ++r) {
+    const int f = tid + r * NT;
+    const int l = f / LS, k = f - (f / LS) * LS;
+    const bool ok = l < L && k < L;
+    const float v = a.theta[ok ? l * L + k : 0];
+    tv[r] = ok ? v : 0.f;
+  }
+
+  const int p = (ty + 1) * HX + (tx + 1);
+#pragma unroll
+  for (int j = 0; j < LG; ++j) {
+    const int l = sub * LG + j;
+    sm.q[l * PS + p] = M::enc((inside && valid[j]) ? __expf(ell[j]) : 0.f);
+  }
+#pragma unroll
+  for (int r = 0; r < HREG; ++r) {
+    const int f = tid + r * NT;
+    if (f < LP * HALO) {
+      const int l = f / HALO;
+      sm.q[l * PS + halo_pos<TX, TY>(f - l * HALO)] = M::enc(__expf(hv[r]));   // exp(-inf) = 0
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < TREG; ++r) {
+    const int f = tid + r * NT;
+    if (f < LP * LS) sm.theta[f] = tv[r];
+  }
+  __syncthreads();
+  if (!inside) return;     // whole groups leave together: the LPN lanes share the node
+
+  // Neighbour sums of this lane's labels.
+  float S[LG];
+#pragma unroll
+  for (int j = 0; j < LG; ++j) {
+    const typename M::T* q = sm.q + (sub * LG + j) * PS + p;
+    float s = M::dec(q[-HX]) + M::dec(q[-1]) + M::dec(q[1]) + M::dec(q[HX]);
+    if (CONN == 8) s += (M::dec(q[-HX - 1]) + M::dec(q[-HX + 1])) + (M::dec(q[HX - 1]) + M::dec(q[HX + 1]));
+    S[j] = s;
+  }
+
+  float z[LG];
+  if (COMPAT == MF_COMPAT_POTTS) {
+    float tot = 0.f;
+#pragma unroll
+    for (int j = 0; j < LG; ++j) tot += S[j];
+    tot = group_sum<LPN>(tot);
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      const float m = uu[j] + a.potts_w * (tot - S[j]);
+      z[j] = valid[j] ? one_minus_alpha * ell[j] - a.alpha * m : -INFINITY;
+    }
+  } else {
+    // every lane needs the whole S of its node
+    float Sa[LP];
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      Sa[0 * LG + j] = group_bcast<LPN, 0>(S[j]);
+      if constexpr (LPN >= 2) Sa[1 * LG + j] = group_bcast<LPN, 1>(S[j]);
+      if constexpr (LPN >= 4) {
+        Sa[2 * LG + j] = group_bcast<LPN, 2>(S[j]);
+        Sa[3 * LG + j] = group_bcast<LPN, 3>(S[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      const float* th = sm.theta + (sub * LG + j) * LS;
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) acc = fmaf(th[k], Sa[k], acc);
+      const float zz = one_minus_alpha * ell[j] - a.alpha * (uu[j] + acc);
+      z[j] = valid[j] ? zz : -INFINITY;
+    }
+  }
+
+  float mx = z[0];
+#pragma unroll
+  for (int j = 1; j < LG; ++j) mx = fmaxf(mx, z[j]);
+  mx = group_max<LPN>(mx);
+  float se = 0.f;
+#pragma unroll
+  for (int j = 0; j < LG; ++j) se += __expf(z[j] - mx);   // exp(-inf) = 0 for empty slots
+  se = group_sum<LPN>(se);
+  const float lse = mx + __logf(se);
+  float* __restrict__ out = a.state_out + base;
+#pragma unroll
+  for (int j = 0; j < LG; ++j) {
+    const int l = sub * LG + j;
+    if (valid[j]) out[(unsigned)l * N + n] = z[j] - lse;
+  }
+}
+
+template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY>
+__global__ __launch_bounds__(TX * TY * LPN) void step_kernel(StepArgs a, float one_minus_alpha) {
+  __shared__ Smem<LG, LPN, TX, TY, PREC> sm;
+  tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY>(a, one_minus_alpha, blockIdx.z, blockIdx.x * TX,
+                                                        blockIdx.y * TY, sm);
+}
+
+// Many independent problems in one launch: slot k owns workgroups
+// [tile_begin[k], tile_begin[k + 1]).
+template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY>
+__global__ __launch_bounds__(TX * TY * LPN) void step_many_kernel(ManyArgs m) {
+  __shared__ Smem<LG, LPN, TX, TY, PREC> sm;
+  const int blk = blockIdx.x;
+  int k = 0;
+  while (k + 1 < m.count && blk >= m.tile_begin[k + 1]) ++k;
+  const int t = blk - m.tile_begin[k];
+  const int tiles_x = (m.slot[k].W + TX - 1) / TX;
+  const int tiles_per_item = tiles_x * ((m.slot[k].H + TY - 1) / TY);
+  const int b = t / tiles_per_item;
+  const int r = t - b * tiles_per_item;
+  const int ty = r / tiles_x, tx = r - (r / tiles_x) * tiles_x;
+  tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY>(m.slot[k], m.one_minus_alpha[k], b, tx * TX, ty * TY, sm);
+}
+
+// Single-step kernels run one lane per node (LPN = 1) on 64 x 4 tiles: of
+// the label splits measured on the 256 x 256, L = 21 grid (1, 2 and 4 lanes
+// per node, 64 x 4 / 32 x 4 / 16 x 4 / 16 x 8 tiles) all took 10-13 us per
+// step there, while on the 2048 x 2048 grid one lane per node streamed
+// fastest (277 us per step against 346-508 us).  The label-parallel split
+// pays off in the fused multi-step kernel (grid_temporal.h) instead.
+inline int slots_for(int L) {
+  return L == 2 ? 2 : L == 21 ? 21 : L <= 4 ? 4 : L <= 8 ? 8 : L <= 16 ? 16 : 32;
+}
+
+inline int tiles(int B, int H, int W, int L) {
+  (void)L;
+  return B * ((W + 63) / 64) * ((H + 3) / 4);
+}
+
+hipError_t launch_f32(const StepArgs& a, int conn, int compat, hipStream_t s);
+hipError_t launch_bf16(const StepArgs& a, int conn, int compat, hipStream_t s);
+hipError_t launch_f16(const StepArgs& a, int conn, int compat, hipStream_t s);
+hipError_t launch_many_f32(const ManyArgs& m, int L, int conn, int compat, hipStream_t s);
+hipError_t launch_many_bf16(const ManyArgs& m, int L, int conn, int compat, hipStream_t s);
+hipError_t launch_many_f16(const ManyArgs& m, int L, int conn, int compat, hipStream_t s);
+
+// Instantiation helper used by the per-precision translation units.
+template <int PREC>
+struct ForPrec {
+  template <int LG, int LPN, int LC, int TX, int TY>
+  static hipError_t one(const StepArgs& a, int conn, int compat, hipStream_t s) {
+    dim3 grid((a.W + TX - 1) / TX, (a.H + TY - 1) / TY, a.B);
+    dim3 block(TX * TY * LPN);
+    const float om = (float)(1.0 - (double)a.alpha);
+    if (conn == 4) {
+      if (compat == MF_COMPAT_POTTS)
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 4, MF_COMPAT_POTTS, PREC, TX, TY>), grid, block, 0, s, a, om);
+      else
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 4, MF_COMPAT_GENERAL, PREC, TX, TY>), grid, block, 0, s, a, om);
+    } else {
+      if (compat == MF_COMPAT_POTTS)
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 8, MF_COMPAT_POTTS, PREC, TX, TY>), grid, block, 0, s, a, om);
+      else
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 8, MF_COMPAT_GENERAL, PREC, TX, TY>), grid, block, 0, s, a, om);
+    }
+    return hipGetLastError();
+  }
+  template <int LG, int LPN, int LC, int TX, int TY>
+  static hipError_t many(const ManyArgs& m, int conn, int compat, hipStream_t s) {
+    const int total = m.tile_begin[m.count];
+    if (total <= 0) return hipSuccess;
+    dim3 block(TX * TY * LPN);
+    if (conn == 4) {
+      if (compat == MF_COMPAT_POTTS)
+        hipLaunchKernelGGL((step_many_kernel<LG, LPN, LC, 4, MF_COMPAT_POTTS, PREC, TX, TY>), dim3(total), block, 0, s, m);
+      else
+        hipLaunchKernelGGL((step_many_kernel<LG, LPN, LC, 4, MF_COMPAT_GENERAL, PREC, TX, TY>), dim3(total), block, 0, s, m);
+    } else {
+      if (compat == MF_COMPAT_POTTS)
+        hipLaunchKernelGGL((step_many_kernel<LG, LPN, LC, 8, MF_COMPAT_POTTS, PREC, TX, TY>), dim3(total), block, 0, s, m);
+      else
+        hipLaunchKernelGGL((step_many_kernel<LG, LPN, LC, 8, MF_COMPAT_GENERAL, PREC, TX, TY>), dim3(total), block, 0, s, m);
+    }
+    return hipGetLastError();
+  }
+  // L = 2 and L = 21 (the label counts of the benchmark workloads) are
+  // compiled for their exact count; other counts use the next slot size.
+  static hipError_t launch(const StepArgs& a, int conn, int compat, hipStream_t s) {
+    switch (slots_for(a.L)) {
+      case 2: return a.L == 2 ? one<2, 1, 2, 64, 4>(a, conn, compat, s) : one<2, 1, 0, 64, 4>(a, conn, compat, s);
+      case 21: return one<21, 1, 21, 64, 4>(a, conn, compat, s);
+      case 4: return one<4, 1, 0, 64, 4>(a, conn, compat, s);
+      case 8: return one<8, 1, 0, 64, 4>(a, conn, compat, s);
+      case 16: return one<16, 1, 0, 64, 4>(a, conn, compat, s);
+      default: return one<32, 1, 0, 64, 4>(a, conn, compat, s);
+    }
+  }
+  static hipError_t launch_many(const ManyArgs& m, int L, int conn, int compat, hipStream_t s) {
+    switch (slots_for(L)) {
+      case 2: return L == 2 ? many<2, 1, 2, 64, 4>(m, conn, compat, s) : many<2, 1, 0, 64, 4>(m, conn, compat, s);
+      case 21: return many<21, 1, 21, 64, 4>(m, conn, compat, s);
+      case 4: return many<4, 1, 0, 64, 4>(m, conn, compat, s);
+      case 8: return many<8, 1, 0, 64, 4>(m, conn, compat, s);
+      case 16: return many<16, 1, 0, 64, 4>(m, conn, compat, s);
+      default: return many<32, 1, 0, 64, 4>(m, conn, compat, s);
+    }
+  }
+};
+
+}  // namespace lanes
+}  // namespace mf

@@ -6,12 +6,11 @@
 namespace mf {
 
 int grid_max_steps_per_launch(int L, int prec) {
-  const size_t per = (size_t)(prec == MF_P_F32 ? 12 : 8);
-  const size_t kMax = 160 * 1024;
-  const int lp = L == 2 ? 2 : L == 21 ? 21 : L <= 4 ? 4 : L <= 8 ? 8 : L <= 16 ? 16 : 32;
-  if ((size_t)lp * 24 * 24 * per <= kMax) return 4;
-  if ((size_t)lp * 22 * 22 * per <= kMax) return 3;
-  return 2;
+  switch (prec) {
+    case MF_P_F32: return temporal::ForPrec<P_F32>::kmax(L);
+    case MF_P_BF16MSG: return temporal::ForPrec<P_BF16>::kmax(L);
+    default: return temporal::ForPrec<P_F16>::kmax(L);
+  }
 }
 
 hipError_t launch_grid_multi_step(const StepArgs& a, int conn, int compat, int prec, int K, int ks,

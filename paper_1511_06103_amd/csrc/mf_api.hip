@@ -203,8 +203,9 @@ mf_status enqueue_init(mf_handle* h) {
   return MF_OK;
 }
 
-// Steps per launch: small grids (fewer 64 x 4 tiles than a few per compute
-// unit) are bound by launch and memory latency, so several steps are fused;
+// Steps per launch: small grids (fewer 64 x 4 tiles than four per compute
+// unit) are bound by launch and memory latency, so three steps are fused
+// (three measured faster than two or four on the 256 x 256, L = 21 grid);
 // large grids stream HBM at one step per launch.
 int choose_steps_per_launch(const mf_desc& d) {
   if (!is_grid(d.graph)) return 1;
@@ -213,7 +214,7 @@ int choose_steps_per_launch(const mf_desc& d) {
   if (k <= 0) {
     const int64_t tiles = (int64_t)d.batch * ((d.width + mf::kTileX - 1) / mf::kTileX) *
                           ((d.height + mf::kTileY - 1) / mf::kTileY);
-    k = tiles >= 4 * 256 ? 1 : kmax;
+    k = tiles >= 4 * 256 ? 1 : (kmax < 3 ? kmax : 3);
   }
   return k < kmax ? k : kmax;
 }
@@ -275,7 +276,7 @@ mf_status enqueue_steps(mf_handle* h, int n) {
     a.alpha = (float)d.alpha;
     a.potts_w = d.potts_w;
     const int conn = d.graph == MF_GRID4 ? 4 : 8;
-    hipError_t e = ks == 1 ? mf::launch_grid_step(a, conn, d.compat, d.precision, h->stream)
+    hipError_t e = ks == 1 ? mf::launch_grid_step_lanes(a, conn, d.compat, d.precision, h->stream)
                            : mf::launch_grid_multi_step(a, conn, d.compat, d.precision, h->k_launch, ks,
                                                         h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -481,9 +482,9 @@ mf_status mf_step_many(mf_handle* const* hs, int32_t count, int32_t n_steps) {
           a.alpha = (float)d.alpha;
           a.potts_w = d.potts_w;
           m.one_minus_alpha[k - c0] = (float)(1.0 - (double)a.alpha);
-          m.tile_begin[k - c0 + 1] = m.tile_begin[k - c0] + mf::grid_tiles(d.batch, d.height, d.width);
+          m.tile_begin[k - c0 + 1] = m.tile_begin[k - c0] + mf::grid_lanes_tiles(d.batch, d.height, d.width, d.n_labels);
         }
-        hipError_t e = mf::launch_grid_step_many(m, dg.n_labels, conn, dg.compat, dg.precision, s);
+        hipError_t e = mf::launch_grid_step_lanes_many(m, dg.n_labels, conn, dg.compat, dg.precision, s);
         if (e != hipSuccess) return fail(grp[c0], MF_EDEVICE, std::string("batched step launch: ") + hipGetErrorString(e));
         for (size_t k = c0; k < c1; ++k) {
           grp[k]->cur ^= 1;
@@ -564,7 +565,7 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
       a.W = d.width;
       a.alpha = (float)d.alpha;
       a.potts_w = d.potts_w;
-      e = mf::launch_grid_step(a, conn, d.compat, d.precision, s);
+      e = mf::launch_grid_step_lanes(a, conn, d.compat, d.precision, s);
       if (e != hipSuccess) return dev_fail(e, "recompute step");
     }
     for (int k = len - 1; k >= 0; --k) {

@@ -143,7 +143,6 @@ struct WorkspaceLayout {
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_init(const float* unary, float* state, int B, int L, int N, int mode,
                        int* flags, hipStream_t s);
-hipError_t launch_grid_step(const StepArgs& a, int conn, int compat, int precision, hipStream_t s);
 // ks <= K sub-steps in one launch of the K-halo kernel; K <= grid_max_steps_per_launch.
 hipError_t launch_grid_multi_step(const StepArgs& a, int conn, int compat, int precision, int K, int ks,
                                   hipStream_t s);
@@ -177,8 +176,9 @@ hipError_t launch_fill_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, size_t n, hipStream_t s);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t s);
 
-int grid_tiles(int B, int H, int W);
-hipError_t launch_grid_step_many(const ManyArgs& m, int L, int conn, int compat, int prec, hipStream_t s);
+int grid_lanes_tiles(int B, int H, int W, int L);
+hipError_t launch_grid_step_lanes(const StepArgs& a, int conn, int compat, int prec, hipStream_t s);
+hipError_t launch_grid_step_lanes_many(const ManyArgs& m, int L, int conn, int compat, int prec, hipStream_t s);
 
 int grid_blocks_per_item(int H, int W);
 
