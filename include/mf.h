@@ -155,6 +155,10 @@ mf_status mf_solve(mf_handle *h, int32_t iters, float *q_out);
  * KL(Q || P) - log Z (Eq. 5).  Synchronises the stream. */
 mf_status mf_free_energy(mf_handle *h, double *F_host);
 
+/* Enqueue q = exp(log q) of the current state into q_out [B][L][N]
+ * (device): the mean parameters of Eq. 4 (Sec. 2.2).  Asynchronous. */
+mf_status mf_marginals(mf_handle *h, float *q_out);
+
 /* Synchronise the stream and report deferred device errors:
  * MF_ENONFINITE if a non-finite unary was seen, MF_EDEVICE on a HIP error. */
 mf_status mf_check(mf_handle *h);

@@ -411,6 +411,15 @@ mf_status mf_free_energy(mf_handle* h, double* F_host) {
   return mf_check(h);
 }
 
+mf_status mf_marginals(mf_handle* h, float* q_out) {
+  if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
+  if (!q_out || ((uintptr_t)q_out & 3u)) return fail(h, MF_EINVAL, "q_out is NULL or misaligned");
+  const size_t elems = (size_t)h->d.batch * h->d.n_labels * h->d.n_nodes;
+  hipError_t e = mf::launch_exp(buf(h, h->cur), q_out, elems, h->stream);
+  if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("exp launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
 mf_status mf_check(mf_handle* h) {
   if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
   int flag = 0;

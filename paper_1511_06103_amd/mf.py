@@ -63,6 +63,7 @@ SIGNATURES = {
     "mf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mf_free_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "mf_check": (ctypes.c_int, [ctypes.c_void_p]),
+    "mf_marginals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mf_current_state": (ctypes.c_void_p, [ctypes.c_void_p]),
     "mf_iteration": (ctypes.c_int32, [ctypes.c_void_p]),
     "mf_steps_per_launch": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -239,6 +240,16 @@ class MeanField:
             if tuple(q_out.shape) != self.shape:
                 raise ValueError("q_out must be [B, L, N]")
         _check(lib().mf_solve(self._h(), int(iters), _ptr(q_out)), self._handle)
+        return q_out
+
+    def marginals(self, q_out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """q = exp(log q) of the current state, written by the library into q_out [B, L, N]."""
+        if q_out is None:
+            q_out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        _dev_tensor(q_out, torch.float32, "q_out", self.device)
+        if tuple(q_out.shape) != self.shape:
+            raise ValueError("q_out must be [B, L, N]")
+        _check(lib().mf_marginals(self._h(), _ptr(q_out)), self._handle)
         return q_out
 
     def free_energy(self) -> np.ndarray:

@@ -1,0 +1,87 @@
+"""Continuous-batching server: every result equals, bitwise, the same request
+solved alone on the plain path; admission respects the memory budget; bad
+requests are rejected without disturbing the others; results match the
+FP64 oracle within the BF16-message per-step bound."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import cases  # noqa: E402
+import oracle as O  # noqa: E402
+from paper_1511_06103_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def small_requests(n=12, seed=41, iters=20, rate=2000.0):
+    from paper_1511_06103_amd import serving
+    trace = synth.serving_trace(seed, n, rate, side_lo=16, side_hi=80)
+    return serving.requests_from_trace(trace, iters=iters)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f32"])
+def test_served_results_equal_alone_bitwise(precision):
+    from paper_1511_06103_amd import serving
+    reqs = small_requests()
+    srv = serving.Server(precision=precision)
+    st = srv.run(reqs, realtime=True)
+    assert st.n_done == len(reqs) and st.n_rejected == 0
+    assert st.max_active >= 2          # requests overlapped on the device
+    for r in reqs:
+        alone = serving.solve_alone(r, precision)
+        np.testing.assert_array_equal(r.q, alone)
+        assert r.latency_s > 0
+
+
+def test_budget_forces_queueing():
+    from paper_1511_06103_amd import serving
+    reqs = small_requests(10, seed=42)
+    budget = max(serving.footprint_bytes(r) for r in reqs) * 2
+    srv = serving.Server(budget_bytes=budget)
+    st = srv.run(reqs, realtime=False)
+    assert st.n_done == 10
+    assert st.max_used_bytes <= budget
+    assert st.max_active < 10
+    assert any(r.t_admit > r.arrival_s + 1e-6 for r in reqs)     # someone waited for memory
+    for r in reqs[::3]:
+        np.testing.assert_array_equal(r.q, serving.solve_alone(r))
+
+
+def test_bad_requests_are_isolated():
+    from paper_1511_06103_amd import serving
+    reqs = small_requests(6, seed=43)
+    bad_nan = serving.SolveRequest(100, 0.0, reqs[0].unary.copy(), reqs[0].theta, reqs[0].height, reqs[0].width,
+                                   iters=20)
+    bad_nan.unary[0, 0, 3] = np.nan
+    bad_shape = serving.SolveRequest(101, 0.0, reqs[1].unary, reqs[1].theta, reqs[1].height + 1, reqs[1].width,
+                                     iters=20)
+    huge = serving.SolveRequest(102, 0.0, np.zeros((1, 21, 512 * 512), np.float32), reqs[2].theta[:1, :1].repeat(21, 0).repeat(21, 1),
+                                512, 512, iters=20)
+    budget = max(serving.footprint_bytes(r) for r in reqs) * 3
+    srv = serving.Server(budget_bytes=budget)
+    st = srv.run(reqs + [bad_nan, bad_shape, huge], realtime=False)
+    assert st.n_done == 6 and st.n_rejected == 3
+    assert bad_nan.status == bad_shape.status == huge.status == "rejected"
+    for r in reqs:
+        np.testing.assert_array_equal(r.q, serving.solve_alone(r))
+
+
+def test_served_results_match_oracle():
+    from paper_1511_06103_amd import serving
+    reqs = small_requests(4, seed=44, iters=1)
+    serving.Server(precision="f32").run(reqs, realtime=False)
+    for r in reqs:
+        inst = synth.Instance(name="r", graph=synth.GRID8, n_labels=r.n_labels, n_nodes=r.n_nodes,
+                              height=r.height, width=r.width, unary=r.unary, theta=r.theta, alpha=r.alpha, iters=1)
+        ref = O.solve(cases.oracle_model(inst), r.alpha, 1)[-1]
+        assert np.abs(r.q[0] - np.exp(ref)).max() <= 1e-6
