@@ -12,9 +12,9 @@ Theta, alpha = 0.5 and T = 100 iterations (FP32).
 
 Prints one JSON line: node-label updates/s = B * N * L * T * K / time, with
 p50/p99 solve latency, the roofline of the dominant kernel (the step kernel
-as the solve launches it, K fused steps per launch, timed per launch with HIP
-events on the stream it runs on) and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+as the solve launches it, K fused steps per launch, timed over back-to-back
+launches between HIP events on the stream it runs on) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
 
 Profiling helpers (single GPU):
     --mode kernel   only the dominant kernel, --launches times (for counters)
@@ -76,18 +76,33 @@ def make_solver(inst, torch, mf):
 def time_step_launches(solver, torch, launches):
     """Average duration of one launch of the step kernel as the solve runs it:
     each mf_step(K) with K = steps fused per launch is exactly one launch.
-    HIP events are recorded around each launch on the solver's stream."""
+    The launches run back to back on the solver's stream between one pair of
+    HIP events, as inside a solve, so the average includes no per-launch
+    event overhead (only the inter-kernel gap of a queued stream)."""
     stream = solver.stream
     k = solver.steps_per_launch
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
-    with torch.cuda.stream(stream):
-        for a, b in ev:
-            a.record(stream)
-            solver.step(k)
-            b.record(stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    solver.step(k)
     torch.cuda.synchronize()
-    d = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
-    return float(d.mean()), float(np.median(d)), k
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        for _ in range(launches):
+            solver.step(k)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e-3 / launches, k
+
+
+def step_kernel_name(inst, k):
+    """The kernel one mf_step(k) launches for this workload (the library's
+    dispatch rule: fused steps for k > 1, Theta S on the matrix cores for a
+    general Theta with 8 < L <= 32)."""
+    L = inst.unary.shape[1]
+    if k == 1:
+        return "mf::lanes::step_kernel"
+    if inst.theta is not None and 8 < L <= 32:
+        return "mf::temporal::multi_step_mfma_kernel"
+    return "mf::temporal::multi_step_kernel"
 
 
 def cpu_baseline(inst, budget_s=12.0):
@@ -115,17 +130,20 @@ def cpu_baseline(inst, budget_s=12.0):
                       f"({el:.1f} s, 1 thread)"}
 
 
-def load_traffic(k):
-    """HBM bytes per launch measured with rocprofv3 counters (profiles/), or
-    None when the kernel sources changed since they were taken."""
+def load_traffic(workload, k):
+    """HBM bytes per launch of the dominant kernel measured with rocprofv3
+    counters (profiles/), or None when none was taken for this workload and
+    launch depth or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != source_hash() or t.get("steps_per_launch") != k:
-        return None
-    return t.get("hbm_bytes_per_launch")
+    for e in t.get("entries", []):
+        if (e.get("workload") == workload and e.get("steps_per_launch") == k
+                and e.get("kernel_source_sha256_16") == source_hash()):
+            return e.get("hbm_bytes_per_launch")
+    return None
 
 
 def main():
@@ -199,16 +217,17 @@ def main():
     log(f"timed {args.steps} solves: wall {wall * 1e3:.3f} ms, HIP events {ev_total * 1e3:.3f} ms")
 
     # dominant kernel: one step-kernel launch = K steps over all B * N * L node-labels
-    mean_d, med_d, k = time_step_launches(solver, torch, args.launches)
+    mean_d, k = time_step_launches(solver, torch, args.launches)
     algo = BYTES_PER_UPDATE * B * N * L * k
     achieved = algo / mean_d / 1e9
-    traffic = load_traffic(k)
-    kname = "mf::temporal::multi_step_kernel" if k > 1 else "mf::lanes::step_kernel"
+    traffic = load_traffic(inst.name, k)
+    kname = step_kernel_name(inst, k)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "steps_per_launch": k, "launch_us_mean": round(mean_d * 1e6, 3),
-                "launch_us_median": round(med_d * 1e6, 3), "algorithmic_bytes_per_launch": algo}
-    log(f"{kname} (K={k}): {mean_d * 1e6:.2f} us mean, {med_d * 1e6:.2f} us median per launch -> {achieved:.0f} GB/s")
+                "algorithmic_bytes_per_launch": algo}
+    log(f"{kname} (K={k}): {mean_d * 1e6:.2f} us mean per launch over {args.launches} back-to-back "
+        f"launches -> {achieved:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu:

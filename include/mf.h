@@ -48,6 +48,10 @@ extern "C" {
 
 #define MF_ABI_VERSION 1
 #define MF_MAX_LABELS 32   /* largest label count the step kernels accept */
+/* n_labels * n_nodes of one problem must stay below this (2^30): the kernels
+   address one problem's [L][N] planes with 32-bit byte offsets.  Larger
+   problems are rejected with MF_EUNSUPPORTED. */
+#define MF_MAX_LABEL_NODES ((size_t)1 << 30)
 
 typedef enum {
   MF_OK = 0,

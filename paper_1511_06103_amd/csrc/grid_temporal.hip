@@ -5,11 +5,11 @@
 
 namespace mf {
 
-int grid_max_steps_per_launch(int L, int prec) {
+int grid_max_steps_per_launch(int L, int compat, int prec) {
   switch (prec) {
-    case MF_P_F32: return temporal::ForPrec<P_F32>::kmax(L);
-    case MF_P_BF16MSG: return temporal::ForPrec<P_BF16>::kmax(L);
-    default: return temporal::ForPrec<P_F16>::kmax(L);
+    case MF_P_F32: return temporal::ForPrec<P_F32>::kmax(L, compat);
+    case MF_P_BF16MSG: return temporal::ForPrec<P_BF16>::kmax(L, compat);
+    default: return temporal::ForPrec<P_F16>::kmax(L, compat);
   }
 }
 

@@ -108,6 +108,10 @@ mf_status check_desc(const mf_desc* d, std::string* msg) {
     *msg = "n_labels above MF_MAX_LABELS";
     return MF_EUNSUPPORTED;
   }
+  if ((size_t)d->n_labels * (size_t)d->n_nodes >= MF_MAX_LABEL_NODES) {
+    *msg = "n_labels * n_nodes must be below MF_MAX_LABEL_NODES per problem";
+    return MF_EUNSUPPORTED;
+  }
   if (d->graph == MF_CSR) {
     if (!d->csr_row_ptr) return bad("csr_row_ptr is NULL");
     if (d->csr_nnz < 0 || d->csr_nnz > INT32_MAX) return bad("csr_nnz out of range");
@@ -203,18 +207,22 @@ mf_status enqueue_init(mf_handle* h) {
   return MF_OK;
 }
 
-// Steps per launch: small grids (fewer 64 x 4 tiles than four per compute
-// unit) are bound by launch and memory latency, so three steps are fused
-// (three measured faster than two or four on the 256 x 256, L = 21 grid);
-// large grids stream HBM at one step per launch.
+// Steps per launch: small grids are bound by launch and memory latency, so
+// several steps are fused.  Where Theta S runs on the matrix cores (general
+// Theta, 8 < L <= 32) four steps are fused below sixteen 64 x 4 tiles per
+// compute unit (measured: 256 x 256 and 16 x 128 x 128 at L = 21 are fastest
+// at four, 2048 x 2048 at one); the VALU kernel fuses three below four tiles
+// per compute unit (three measured faster than two or four).  Larger grids
+// stream HBM at one step per launch.
 int choose_steps_per_launch(const mf_desc& d) {
   if (!is_grid(d.graph)) return 1;
-  const int kmax = mf::grid_max_steps_per_launch(d.n_labels, d.precision);
+  const int kmax = mf::grid_max_steps_per_launch(d.n_labels, d.compat, d.precision);
   int k = d.steps_per_launch;
   if (k <= 0) {
     const int64_t tiles = (int64_t)d.batch * ((d.width + mf::kTileX - 1) / mf::kTileX) *
                           ((d.height + mf::kTileY - 1) / mf::kTileY);
-    k = tiles >= 4 * 256 ? 1 : (kmax < 3 ? kmax : 3);
+    const bool mfma = d.compat == MF_COMPAT_GENERAL && d.n_labels > 8 && d.n_labels <= 32;
+    k = mfma ? (tiles >= 16 * 256 ? 1 : 4) : (tiles >= 4 * 256 ? 1 : 3);
   }
   return k < kmax ? k : kmax;
 }

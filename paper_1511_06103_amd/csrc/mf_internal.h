@@ -146,7 +146,7 @@ hipError_t launch_init(const float* unary, float* state, int B, int L, int N, in
 // ks <= K sub-steps in one launch of the K-halo kernel; K <= grid_max_steps_per_launch.
 hipError_t launch_grid_multi_step(const StepArgs& a, int conn, int compat, int precision, int K, int ks,
                                   hipStream_t s);
-int grid_max_steps_per_launch(int L, int precision);
+int grid_max_steps_per_launch(int L, int compat, int precision);
 hipError_t launch_grid_free_energy(const FreeEnergyArgs& a, int conn, int compat, double* f_out,
                                    hipStream_t s);
 hipError_t launch_clear_flags(int* flags, int n, hipStream_t s);

@@ -109,6 +109,16 @@ def test_too_many_labels_unsupported():
     assert validate(good_desc(n_labels=mf.MF_MAX_LABELS + 1)) == mf.MF_EUNSUPPORTED
 
 
+def test_label_node_limit():
+    """One problem's L * N must stay below 2^30 (32-bit byte offsets in the kernels)."""
+    far = dict(state=FAKE + (1 << 36), workspace=FAKE + (1 << 38), workspace_bytes=1 << 40)
+    ok = good_desc(n_labels=1, height=32767, width=32769, n_nodes=32767 * 32769, **far)
+    assert validate(ok) == mf.MF_OK
+    big = good_desc(n_labels=32, height=8192, width=4096, n_nodes=8192 * 4096, **far)
+    assert validate(big) == mf.MF_EUNSUPPORTED
+    assert "MF_MAX_LABEL_NODES" in mf.last_error()
+
+
 def test_workspace_checks():
     d = good_desc()
     need = mf.lib().mf_workspace_size(ctypes.byref(d))

@@ -228,7 +228,11 @@ def test_shapes_end_to_end(H, W, L, conn, potts, B, alpha):
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 @pytest.mark.parametrize("H,W,L,conn,potts,B,alpha", [
     (37, 70, 5, synth.GRID8, False, 2, 0.3),
+    (33, 131, 13, synth.GRID8, False, 1, 0.5),
+    (19, 40, 17, synth.GRID8, False, 2, 0.5),
+    (40, 33, 21, synth.GRID8, False, 1, 0.6),
     (20, 67, 21, synth.GRID4, False, 1, 0.5),
+    (7, 3, 21, synth.GRID8, False, 1, 0.5),
     (9, 200, 24, synth.GRID8, True, 1, 0.4),
     (30, 30, 32, synth.GRID8, False, 1, 0.5),
     (50, 45, 2, synth.GRID8, True, 1, 0.5),
@@ -254,6 +258,20 @@ def test_fused_steps_from_identical_state(c2, k):
     ref = O.solve(model, 0.5, k, ell0=start.astype(np.float64))[-1]
     err = cases.max_dq(gpu_state(s)[0], ref)
     assert err <= 1e-6 * k, (k, err)
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16", 2e-3), ("f16", 2e-4)])
+@pytest.mark.parametrize("k", [2, 3])
+def test_fused_steps_reduced_precision(c2, precision, tol, k):
+    """Fused steps with BF16 / FP16 message operands stay within the per-step
+    message-precision bound times the number of steps."""
+    inst, model, traj = c2
+    start = traj[20].astype(np.float32)
+    s = solver_from_state(inst, start[None], steps_per_launch=k, precision=precision)
+    s.step(k)
+    ref = O.solve(model, 0.5, k, ell0=start.astype(np.float64))[-1]
+    err = cases.max_dq(gpu_state(s)[0], ref)
+    assert err <= tol * k, (precision, k, err)
 
 
 def test_batch16_workload_end_to_end():
