@@ -217,6 +217,33 @@ mf_status mf_backward(mf_handle *h, const float *ckpt_states, int32_t T, int32_t
                       const float *grad_logq_T, float *grad_unary, float *grad_theta,
                       void *work, size_t work_bytes);
 
+/* Lipschitz constant L-hat of the gradient of the expected energy on the
+ * tangent space of the product of simplices: the largest eigenvalue of the
+ * Hessian H of the pairwise (and co-occurrence) energy restricted to
+ * label vectors that sum to zero at every node.  The step is admissible
+ * for d > L-hat, i.e. alpha < 1 / (1 + L-hat) (Sec. 3.2; the paper
+ * estimates L-hat by the power method, Sec. 3.2 and Fig. 2).  With P the
+ * per-node centring, two runs of the power method:
+ *   run 1 on P H P from P v0:  rho = |P H P v| / |v| at the last iteration
+ *          (the spectral radius; |.| the Euclidean norm over all node-labels);
+ *   run 2 on P H P + rho I from P v1 / |P v1|:  the Rayleigh quotient
+ *          lambda_max + rho at the last iteration.
+ * H does not depend on the unaries or the batch: item 0's graph is used.
+ * v0, v1: device [L][N] FP32 start vectors (any values; centred inside).
+ * iters >= 1: iterations of each run (a fixed count, as a solve's).
+ * work: device scratch of mf_lipschitz_workspace_size bytes, 256-aligned.
+ * lambda_max, rho: host.  FP32 Hessian-vector products, FP64 sums.
+ * Synchronises the stream; does not change the state of h.  L = 1 gives
+ * 0 and 0 (the tangent space is {0}); a run whose iterate vanishes stops
+ * there (lambda_max = -rho when run 2 vanishes). */
+/* The admissible fixed step of Sec. 3.2: alpha = 1 / (1 + d) with
+ * d = margin * L-hat (d > L-hat needs margin > 1; a margin below 1 is taken
+ * as 1).  L-hat <= 0 (or NaN) gives alpha = 1, the fully parallel update. */
+double mf_admissible_alpha(double lipschitz, double margin);
+size_t mf_lipschitz_workspace_size(const mf_handle *h);
+mf_status mf_lipschitz(mf_handle *h, int32_t iters, const float *v0, const float *v1, void *work,
+                       size_t work_bytes, double *lambda_max, double *rho);
+
 /* Build the dense-CRF kernel K_ij = exp(-|f_i - f_j|^2 / 2), K_ii = 0
  * (the Gaussian kernel of the fully connected CRF, Sec. 4.2), rounded to
  * bfloat16 (round to nearest even) into K_bf16 [n][n] (device, uint16 bits).

@@ -494,12 +494,14 @@ def _hv_tangent(v, model):
     return h - h.mean(axis=0, keepdims=True)
 
 
-def lipschitz_power(model, iters=3000, seed=0):
+def lipschitz_power(model, iters=3000, seed=0, v0=None, v1=None):
     """Largest tangent-space eigenvalue of the Hessian by the power method (Sec. 3.2
     and the orange lines of Fig. 2, Sec. 4.3).
 
     Plain power iteration on P H P gives the spectral radius rho; a second run
     on P H P + rho I gives lambda_max + rho.  Returns (lambda_max, rho).
+    The start vectors are standard normal draws of default_rng(seed), in the
+    order (first run, second run), unless given as v0 and v1.
     """
     rng = np.random.default_rng(seed)
     L, N = model.unary.shape
@@ -507,7 +509,7 @@ def lipschitz_power(model, iters=3000, seed=0):
         return 0.0, 0.0
 
     def power(shift):
-        v = rng.standard_normal((L, N))
+        v = rng.standard_normal((L, N)) if v1 is None else np.array(v1, dtype=np.float64)
         v -= v.mean(axis=0, keepdims=True)
         v /= np.linalg.norm(v)
         lam = 0.0
@@ -520,7 +522,7 @@ def lipschitz_power(model, iters=3000, seed=0):
             v = w / nrm
         return lam
 
-    v = rng.standard_normal((L, N))
+    v = rng.standard_normal((L, N)) if v0 is None else np.array(v0, dtype=np.float64)
     v -= v.mean(axis=0, keepdims=True)
     rho = 0.0
     for _ in range(iters):

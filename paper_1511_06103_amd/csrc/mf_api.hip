@@ -617,6 +617,118 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
   return MF_OK;
 }
 
+// Workspace of mf_lipschitz: two [L][N] iterates, the scalars, the FP64
+// partial sums of one launch.
+struct LipLayout {
+  size_t a = 0, b = 0, sc = 0, res = 0, part = 0, total = 0;
+  int np = 3, blocks = 0;
+};
+
+LipLayout lip_layout(const mf_desc& d) {
+  LipLayout l;
+  const size_t LN = (size_t)d.n_labels * d.n_nodes;
+  l.np = d.graph == MF_DENSE ? 3 + MF_MAX_LABELS : 3;
+  const int hb = mf::lip_blocks(d.graph, d.n_nodes, d.height, d.width);
+  const int cb = (d.n_nodes + 255) / 256;
+  l.blocks = hb > cb ? hb : cb;
+  size_t off = 0;
+  l.a = off;
+  off += align256(sizeof(float) * LN);
+  l.b = off;
+  off += align256(sizeof(float) * LN);
+  l.sc = off;
+  off += align256(sizeof(double) * (2 + MF_MAX_LABELS));
+  l.res = off;
+  off += align256(sizeof(double) * 4);
+  l.part = off;
+  off += align256(sizeof(double) * (size_t)l.blocks * l.np);
+  l.total = off;
+  return l;
+}
+
+double mf_admissible_alpha(double lipschitz, double margin) {
+  if (!(lipschitz > 0.0)) return 1.0;
+  if (!(margin >= 1.0)) margin = 1.0;
+  return 1.0 / (1.0 + margin * lipschitz);
+}
+
+size_t mf_lipschitz_workspace_size(const mf_handle* h) {
+  if (!h) return 0;
+  return lip_layout(h->d).total;
+}
+
+mf_status mf_lipschitz(mf_handle* h, int32_t iters, const float* v0, const float* v1, void* work,
+                       size_t work_bytes, double* lambda_max, double* rho) {
+  if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
+  const mf_desc& d = h->d;
+  if (iters < 1) return fail(h, MF_EINVAL, "need iters >= 1");
+  if (!v0 || !v1 || !work || !lambda_max || !rho) return fail(h, MF_EINVAL, "NULL argument");
+  if (((uintptr_t)v0 | (uintptr_t)v1) & 3u) return fail(h, MF_EINVAL, "start vectors must be 4-byte aligned");
+  if ((uintptr_t)work & 255u) return fail(h, MF_EINVAL, "work must be 256-byte aligned");
+  const LipLayout lay = lip_layout(d);
+  if (work_bytes < lay.total) return fail(h, MF_ENOWORKSPACE, "work smaller than mf_lipschitz_workspace_size");
+  if (d.n_labels == 1) {   // the tangent space is {0}
+    *lambda_max = 0.0;
+    *rho = 0.0;
+    return MF_OK;
+  }
+  char* base = (char*)work;
+  float* A = (float*)(base + lay.a);
+  float* Bv = (float*)(base + lay.b);
+  mf::LipArgs a;
+  a.sc = (double*)(base + lay.sc);
+  a.res = (double*)(base + lay.res);
+  a.part = (double*)(base + lay.part);
+  a.np = lay.np;
+  a.graph = d.graph;
+  a.compat = d.compat;
+  a.L = d.n_labels;
+  a.N = d.n_nodes;
+  a.H = d.height;
+  a.W = d.width;
+  a.potts_w = d.potts_w;
+  a.theta = d.theta;
+  a.row_ptr = d.csr_row_ptr;
+  a.col = d.csr_col;
+  a.csr_w = d.csr_w;
+  a.nnz = d.csr_nnz;
+  a.K = (const uint16_t*)d.dense_K;
+  a.cooc = d.cooc;
+  const hipStream_t s = h->stream;
+  const int cblocks = (d.n_nodes + 255) / 256;
+  const int hblocks = mf::lip_blocks(d.graph, d.n_nodes, d.height, d.width);
+  auto dev_fail = [&](hipError_t e, const char* what) {
+    return fail(h, MF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  // run 1 on P H P (spectral radius), run 2 on P H P + rho I (lambda_max + rho)
+  for (int run = 0; run < 2; ++run) {
+    a.v = nullptr;
+    a.w = A;
+    hipError_t e = mf::launch_lip_center(a, run == 0 ? v0 : v1, s);
+    if (e == hipSuccess) e = mf::launch_lip_reduce(a, cblocks, run == 0 ? 0 : 1, s);
+    if (e != hipSuccess) return dev_fail(e, "power method start");
+    float* cur = A;
+    float* nxt = Bv;
+    for (int t = 0; t < iters; ++t) {
+      a.v = cur;
+      a.w = nxt;
+      e = mf::launch_lip_hvp(a, s);
+      if (e == hipSuccess) e = mf::launch_lip_reduce(a, hblocks, run == 0 ? 2 : 3, s);
+      if (e != hipSuccess) return dev_fail(e, "power iteration");
+      float* t2 = cur;
+      cur = nxt;
+      nxt = t2;
+    }
+  }
+  double res[2];
+  hipError_t e = hipMemcpyAsync(res, a.res, sizeof(res), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "power method result");
+  *rho = res[0];
+  *lambda_max = res[1] - res[0];
+  return MF_OK;
+}
+
 mf_status mf_dense_kernel(const float* features, int32_t n, int32_t dim, uint16_t* K_bf16, void* stream) {
   if (!features || !K_bf16) return fail(nullptr, MF_EINVAL, "features or K is NULL");
   if (n < 1 || dim < 1 || dim > 16) return fail(nullptr, MF_EINVAL, "need n >= 1 and 1 <= dim <= 16");

@@ -92,6 +92,25 @@ struct DenseStepArgs {
   float alpha, potts_w, inv_n;
 };
 
+// Power method for the tangent-space Lipschitz constant (lipschitz_kernels.hip).
+struct LipArgs {
+  const float* v;          // [L][N] current iterate, before its scale
+  float* w;                // [L][N] output
+  double* sc;              // [2 + MF_MAX_LABELS]: scale of v, shift, column sums T of scaled v
+  double* res;             // [4]: rho, lambda, run-1 stopped, run-2 stopped
+  double* part;            // [blocks][np] FP64 partial sums
+  int np;                  // 3, or 3 + MF_MAX_LABELS on a dense graph (column sums)
+  int graph, compat, L, N, H, W;
+  float potts_w;
+  const float* theta;      // [L][L] (general)
+  const int32_t* row_ptr;  // CSR
+  const int32_t* col;
+  const float* csr_w;
+  long long nnz;
+  const uint16_t* K;       // dense [N][N] bf16 bits
+  const float* cooc;       // dense co-occurrence [L][L] or nullptr
+};
+
 struct DenseGeometry {
   int Np = 0, NRB = 0, KS = 0, jchunk = 0;
 };
@@ -150,6 +169,10 @@ int grid_max_steps_per_launch(int L, int compat, int precision);
 hipError_t launch_grid_free_energy(const FreeEnergyArgs& a, int conn, int compat, double* f_out,
                                    hipStream_t s);
 hipError_t launch_clear_flags(int* flags, int n, hipStream_t s);
+hipError_t launch_lip_center(const LipArgs& a, const float* v0, hipStream_t s);
+hipError_t launch_lip_hvp(const LipArgs& a, hipStream_t s);
+hipError_t launch_lip_reduce(const LipArgs& a, int n_blocks, int mode, hipStream_t s);
+int lip_blocks(int graph, int N, int H, int W);
 hipError_t launch_exp(const float* state, float* q, size_t count, hipStream_t s);
 hipError_t launch_dense_kernel(const float* f, int n, int dim, uint16_t* K, hipStream_t s);
 int dense_planes(int precision);

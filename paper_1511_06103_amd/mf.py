@@ -76,6 +76,11 @@ SIGNATURES = {
     "mf_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_size_t]),
+    "mf_lipschitz_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "mf_lipschitz": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
+    "mf_admissible_alpha": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
 }
 
 _lib = None
@@ -98,6 +103,11 @@ def lib():
             raise RuntimeError("mf_desc layout mismatch between the binding and libmf.so")
         _lib = L
     return _lib
+
+
+def admissible_alpha(lipschitz: float, margin: float = 1.01) -> float:
+    """alpha = 1 / (1 + margin * L-hat) (mf_admissible_alpha)."""
+    return float(lib().mf_admissible_alpha(float(lipschitz), float(margin)))
 
 
 def last_error(handle=None):
@@ -277,6 +287,23 @@ class MeanField:
                                  _ptr(gu), _ptr(gt), _ptr(work), nbytes), self._handle)
         self._bwd_work = work    # keep alive until the stream has consumed it
         return gu, gt
+
+    def lipschitz(self, v0: torch.Tensor, v1: torch.Tensor, iters: int = 3000):
+        """Tangent-space Lipschitz constant by the power method (mf_lipschitz).
+
+        v0, v1: device [L, N] FP32 start vectors of the two runs.  Returns
+        (lambda_max, rho): the largest eigenvalue and the spectral radius."""
+        _, L, N = self.shape
+        for name, v in (("v0", v0), ("v1", v1)):
+            _dev_tensor(v, torch.float32, name, self.device)
+            if tuple(v.shape) != (L, N):
+                raise ValueError(f"{name} must be [L, N]")
+        nbytes = lib().mf_lipschitz_workspace_size(self._h())
+        work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        lam, rho = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mf_lipschitz(self._h(), int(iters), _ptr(v0), _ptr(v1), _ptr(work), nbytes,
+                                  ctypes.byref(lam), ctypes.byref(rho)), self._handle)
+        return lam.value, rho.value
 
     def check(self):
         _check(lib().mf_check(self._h()), self._handle)

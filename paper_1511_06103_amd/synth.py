@@ -197,6 +197,16 @@ def workload_c3():
     return dense_instance(3, 4096, 21, 64.0, 0.5, 50, 1.0, True, name="dense4096_L21_cooc")
 
 
+def power_start_vectors(seed, n_labels, n_nodes):
+    """Start vectors of the two power-method runs, [L, N] each, standard
+    normal in FP64 from default_rng(seed) in the order (v0, v1), rounded to
+    FP32 (the values both the device and the oracle start from)."""
+    rng = np.random.default_rng(seed)
+    v0 = rng.standard_normal((n_labels, n_nodes))
+    v1 = rng.standard_normal((n_labels, n_nodes))
+    return _f32(v0), _f32(v1)
+
+
 def random_csr_graph(rng, n_nodes, avg_degree, weighted=True):
     """Symmetric random graph in CSR form (rows sorted, no self loops, no duplicates).
 

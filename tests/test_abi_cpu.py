@@ -183,3 +183,12 @@ def test_csr_workspace_holds_node_major_q():
     c = mf.lib().mf_workspace_size(ctypes.byref(csr_desc()))
     # two node-major copies of q, L = 21 padded to 24
     assert c - g >= 2 * 64 * 64 * 24 * 4
+
+
+def test_admissible_alpha_rule():
+    """alpha = 1 / (1 + margin * L-hat) of Sec. 3.2, computed by the library (host code)."""
+    assert mf.admissible_alpha(0.0) == 1.0
+    assert mf.admissible_alpha(-3.0) == 1.0
+    assert mf.admissible_alpha(float("nan")) == 1.0
+    assert abs(mf.admissible_alpha(3.981888) - 1 / (1 + 1.01 * 3.981888)) < 1e-15
+    assert abs(mf.admissible_alpha(2.0, 0.5) - 1 / 3) < 1e-15     # margin below 1 taken as 1

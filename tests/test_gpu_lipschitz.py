@@ -1,0 +1,124 @@
+"""Device power method for the tangent-space Lipschitz constant (Sec. 3.2):
+the same two runs as the FP64 oracle from the same start vectors on grids,
+CSR and dense graphs, the closed form on grids, and the admissible step it
+gives (the free energy decreases at every step)."""
+import dataclasses
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import cases  # noqa: E402
+import oracle as O  # noqa: E402
+from paper_1511_06103_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _instance(which):
+    if which == "grid8_theta_L21":
+        return synth.grid_theta_random(31, 40, 37, 21, synth.GRID8, alpha=0.5, iters=1)
+    if which == "grid4_potts_L2":
+        return synth.workload_c1()
+    if which == "grid8_theta_L5_batch":
+        return synth.grid_theta_random(32, 17, 23, 5, synth.GRID8, batch=3, alpha=0.5, iters=1)
+    if which == "grid4_theta_L32":
+        return synth.grid_theta_random(33, 9, 30, 32, synth.GRID4, alpha=0.5, iters=1)
+    if which == "csr_theta_L7":
+        return synth.csr_instance(34, 700, 7, avg_degree=6, weighted=True, iters=1)
+    if which == "csr_potts_L3":
+        inst = synth.csr_instance(35, 500, 3, avg_degree=5, weighted=False, iters=1)
+        return dataclasses.replace(inst, compat=synth.COMPAT_POTTS, potts_w=0.7, theta=None)
+    if which == "dense_cooc_L21":
+        return synth.dense_instance(36, 384, 21, iters=1)
+    raise ValueError(which)
+
+
+def _device_lipschitz(inst, iters, seed=7, **kw):
+    v0, v1 = synth.power_start_vectors(seed, inst.n_labels, inst.n_nodes)
+    s = cases.gpu_solver(inst, **kw)
+    lam, rho = s.lipschitz(torch.from_numpy(v0).cuda(), torch.from_numpy(v1).cuda(), iters=iters)
+    return lam, rho, v0, v1
+
+
+def _dense_K(inst):
+    """The device-built BF16 kernel matrix, for both sides (its FP32 exp may
+    round to a neighbouring BF16 value of the FP64 one)."""
+    from paper_1511_06103_amd import mf
+    K = mf.dense_kernel(torch.from_numpy(inst.features).to("cuda:0"))
+    torch.cuda.synchronize()
+    return K, K.float().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("which", ["grid8_theta_L21", "grid4_potts_L2", "grid8_theta_L5_batch",
+                                   "grid4_theta_L32", "csr_theta_L7", "csr_potts_L3", "dense_cooc_L21"])
+def test_power_method_matches_oracle(which):
+    """Same start vectors, same iteration count: FP32 products and FP64 sums
+    against the FP64 oracle, within 2e-5 of the spectral radius."""
+    inst = _instance(which)
+    if inst.graph == synth.DENSE:
+        K, K64 = _dense_K(inst)
+        lam, rho, v0, v1 = _device_lipschitz(inst, iters=150, dense_K=K)
+        model = cases.oracle_model(inst, K=K64)
+    else:
+        lam, rho, v0, v1 = _device_lipschitz(inst, iters=150)
+        model = cases.oracle_model(inst)
+    lam_o, rho_o = O.lipschitz_power(model, iters=150, v0=v0, v1=v1)
+    assert rho_o > 0
+    assert abs(rho - rho_o) <= 2e-5 * rho_o, (rho, rho_o)
+    assert abs(lam - lam_o) <= 2e-5 * rho_o, (lam, lam_o)
+
+
+@pytest.mark.parametrize("which,iters", [("3x3", 6000), ("c1", 6000), ("theta_grid8", 8000)])
+def test_power_method_reaches_closed_form(which, iters):
+    """Converged estimates equal the grid closed form lambda_max(A) mu_max
+    (pinned on the CPU against the eigenvalues of the dense tangent Hessian)."""
+    if which == "3x3":
+        inst = synth.workload_3x3()
+    elif which == "c1":
+        inst = synth.workload_c1()
+    else:
+        inst = synth.grid_theta_random(21, 10, 9, 5, synth.GRID8)
+    lam, rho, _, _ = _device_lipschitz(inst, iters=iters)
+    exact = cases.oracle_lipschitz(inst)
+    assert abs(lam - exact) <= 1e-5 * exact, (lam, exact)
+    assert rho >= exact * (1 - 1e-6)
+
+
+def test_single_label_and_zero_theta():
+    inst = synth.grid_theta_random(37, 8, 8, 1, synth.GRID8, iters=1)
+    lam, rho, _, _ = _device_lipschitz(inst, iters=5)
+    assert lam == 0.0 and rho == 0.0
+    inst = synth.grid_theta_random(38, 8, 8, 4, synth.GRID8, iters=1)
+    inst.theta = np.zeros_like(inst.theta)
+    lam, rho, v0, v1 = _device_lipschitz(inst, iters=5)
+    lam_o, rho_o = O.lipschitz_power(cases.oracle_model(inst), iters=5, v0=v0, v1=v1)
+    assert (lam, rho) == (lam_o, rho_o) == (0.0, 0.0)
+
+
+def test_admissible_alpha_from_device_estimate_decreases_free_energy():
+    """alpha = 1 / (1 + 1.01 L-hat) with the device estimate: F(q^{t+1}) <= F(q^t)
+    on the GPU at every step of a 256 x 256, L = 21 solve (Sec. 3.2)."""
+    from paper_1511_06103_amd import mf
+    inst = synth.workload_c2()
+    lam, _, _, _ = _device_lipschitz(inst, iters=3000)
+    exact = cases.oracle_lipschitz(inst)
+    assert lam <= exact * (1 + 1e-6) and lam >= 0.97 * exact, (lam, exact)
+    alpha = mf.admissible_alpha(lam * 1.02)     # an estimate from below: extra margin
+    assert abs(alpha - O.admissible_alpha(lam * 1.02)) < 1e-15
+    s = cases.gpu_solver(inst, alpha=alpha)
+    F = [s.free_energy()[0]]
+    for _ in range(30):
+        s.step(1)
+        F.append(s.free_energy()[0])
+    assert all(F[t + 1] <= F[t] + 1e-6 * abs(F[t]) for t in range(30)), F
+
