@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MF_ABI_VERSION 1
+#define MF_ABI_VERSION 2
 #define MF_MAX_LABELS 32   /* largest label count the step kernels accept */
 /* n_labels * n_nodes of one problem must stay below this (2^30): the kernels
    address one problem's [L][N] planes with 32-bit byte offsets.  Larger
@@ -83,6 +83,40 @@ typedef enum { MF_P_F32 = 0, MF_P_BF16MSG = 1, MF_P_F16MSG = 2 } mf_precision;
  * by the caller (resume from a checkpoint). */
 typedef enum { MF_INIT_UNARY = 0, MF_INIT_UNIFORM = 1, MF_INIT_STATE = 2 } mf_init_mode;
 
+/* Step rule of mf_step / mf_solve.
+ * FIXED    the parallel proximal step (Eq. 13-15, Sec. 3.1) with the fixed
+ *          step alpha = 1 / (1 + d) of Eq. 16 (Sec. 3.2).
+ * The others (grids with FP32 messages, one step per launch):
+ * ADAPTIVE OURS-ADAPTIVE for binary variables (Eq. 19, Sec. 3.3): node i
+ *          takes alpha_i = 1 / (1 + q_i0 q_i1 d) with d = 1 / alpha - 1.
+ *          L = 2 only.
+ * ADHOC    damping in mean parameters (Eq. 9, Sec. 2.2.2):
+ *          q <- (1 - alpha) q + alpha softmax(-m).
+ * MOMENTUM OURS-MOMENTUM (Eq. 20-21, Sec. 3.4): the message in the step is
+ *          its exponential average mom <- g1 mom + (1 - g1) m (rule_gamma1 =
+ *          g1), used right after the update; mom starts at m(q^0).
+ * ADAM     OURS-ADAM (Eq. 22-23, Sec. 3.5), read as: the momentum average
+ *          above (rule_gamma1); the per node-label second moment
+ *          v <- g2 v + (1 - g2) g^2 of the natural gradient g = m + log q
+ *          centred over labels (rule_gamma2, v^0 = rule_v0); the per
+ *          node-label step d_t = max(sqrt(v) d + rule_eps - 1, 1e-6) with
+ *          d = 1 / alpha - 1, alpha_t = 1 / (1 + d_t).
+ * SWEEP    sequential mean field (Eq. 8, Sec. 2.2.1) as a chromatic
+ *          Gauss-Seidel sweep: nodes are coloured so that neighbours differ
+ *          (2 colours (x + y) mod 2 on 4-connected grids, 4 colours
+ *          (x mod 2) + 2 (y mod 2) on 8-connected grids) and one step
+ *          updates the colours in order, q_i <- softmax(-m_i) with the
+ *          values of the colours already updated: exactly a sequential sweep
+ *          in that node order.  alpha is not used. */
+typedef enum {
+  MF_RULE_FIXED = 0,
+  MF_RULE_ADAPTIVE = 1,
+  MF_RULE_ADHOC = 2,
+  MF_RULE_MOMENTUM = 3,
+  MF_RULE_ADAM = 4,
+  MF_RULE_SWEEP = 5
+} mf_rule;
+
 typedef struct mf_desc {
   int32_t abi_version;     /* must be MF_ABI_VERSION */
   int32_t batch;           /* B >= 1 problems sharing graph, Theta and alpha */
@@ -98,6 +132,11 @@ typedef struct mf_desc {
   int32_t steps_per_launch; /* grids: proximal steps fused into one launch (temporal
                              * blocking); 0 = chosen by the library, 1 = one step per
                              * launch; clamped to what the tile fits in LDS */
+  int32_t rule;            /* mf_rule (MF_RULE_FIXED = 0: the fixed-step proximal update) */
+  float rule_gamma1;       /* MOMENTUM / ADAM: decay of the momentum average, in [0, 1) */
+  float rule_gamma2;       /* ADAM: decay of the second moment, in [0, 1) */
+  float rule_eps;          /* ADAM: epsilon >= 0 */
+  float rule_v0;           /* ADAM: initial second moment >= 0 */
   /* CSR graph (graph == MF_CSR): row_ptr [N + 1] non-decreasing from 0,
    * col [nnz] in [0, N), weights [nnz] or NULL for unit weights.  The free
    * energy assumes the adjacency is symmetric. */
@@ -186,7 +225,7 @@ const char *mf_last_error(const mf_handle *h);
 
 /* Continuous batching: enqueue n_steps >= 0 proximal steps for each of
  * the count handles hs[0..count) in as few launches as possible (grids
- * only).  Handles with the same label count, connectivity, compatibility
+ * with MF_RULE_FIXED only).  Handles with the same label count, connectivity, compatibility
  * kind and precision share a launch; each handle keeps its own sizes,
  * alpha, arrays and iteration counter.  Every handle advances one step per
  * launch, with the same per-tile arithmetic as mf_step at
@@ -210,7 +249,7 @@ mf_status mf_step_many(mf_handle *const *hs, int32_t count, int32_t n_steps);
  * grad_theta:  device [L][L], overwritten with dLoss / dTheta summed over
  *   the batch (for POTTS: the gradient with respect to the implied matrix).
  * work: device scratch of mf_backward_workspace_size bytes, 256-aligned.
- * Grids only (MF_EUNSUPPORTED otherwise).  Asynchronous on the stream of h;
+ * Grids with MF_RULE_FIXED only (MF_EUNSUPPORTED otherwise).  Asynchronous on the stream of h;
  * does not change the state of h. */
 size_t mf_backward_workspace_size(const mf_handle *h, int32_t ckpt_every);
 mf_status mf_backward(mf_handle *h, const float *ckpt_states, int32_t T, int32_t ckpt_every,

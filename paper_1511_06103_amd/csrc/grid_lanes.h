@@ -97,13 +97,135 @@ struct Smem {
   float theta[G::LP * G::LS];
 };
 
+// Normalise z over the valid slots and store z - lse(z) as log q'.
+template <int LG>
+__device__ inline void store_normalised(float* __restrict__ out, const bool (&valid)[LG], const float (&z)[LG],
+                                        unsigned N, unsigned n) {
+  float mx = z[0];
+#pragma unroll
+  for (int j = 1; j < LG; ++j) mx = fmaxf(mx, z[j]);
+  float se = 0.f;
+#pragma unroll
+  for (int j = 0; j < LG; ++j) se += __expf(z[j] - mx);    // exp(-inf) = 0 for empty slots
+  const float lse = mx + __logf(se);
+#pragma unroll
+  for (int j = 0; j < LG; ++j)
+    if (valid[j]) out[(unsigned)j * N + n] = z[j] - lse;
+}
+
+// The update of the non-fixed step rules from the messages mm at one node
+// (one lane per node: slot j is label j).  z holds the fixed-step value.
+template <int LG, int CONN, int RULE>
+__device__ inline void rule_epilogue(const StepArgs& a, const RuleArgs& rx, const bool (&valid)[LG],
+                                     const float (&ell)[LG], const float (&mm)[LG], float (&z)[LG], size_t base,
+                                     unsigned N, unsigned n, int x, int y, int L) {
+  float* __restrict__ out = a.state_out + base;
+  if constexpr (RULE == MF_RULE_ADAPTIVE) {
+    // Eq. 19: d_i = q_i0 q_i1 d, alpha_i = 1 / (1 + d_i) (L = 2)
+    const float qq = __expf(ell[0]) * __expf(ell[1]);
+    const float eta = 1.0f / (1.0f + qq * rx.d);
+#pragma unroll
+    for (int j = 0; j < LG; ++j) z[j] = valid[j] ? (1.0f - eta) * ell[j] - eta * mm[j] : -INFINITY;
+    store_normalised<LG>(out, valid, z, N, n);
+  } else if constexpr (RULE == MF_RULE_ADHOC) {
+    // Eq. 9: q' = (1 - eta) q + eta softmax(-m), eta = alpha
+    float zs[LG];
+#pragma unroll
+    for (int j = 0; j < LG; ++j) zs[j] = valid[j] ? -mm[j] : -INFINITY;
+    float mx = zs[0];
+#pragma unroll
+    for (int j = 1; j < LG; ++j) mx = fmaxf(mx, zs[j]);
+    float se = 0.f;
+#pragma unroll
+    for (int j = 0; j < LG; ++j) se += __expf(zs[j] - mx);
+    const float lse = mx + __logf(se);
+    const float eta = a.alpha;
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      if (valid[j]) {
+        const float qn = (1.0f - eta) * __expf(ell[j]) + eta * __expf(zs[j] - lse);
+        out[(unsigned)j * N + n] = __logf(qn);
+      }
+    }
+  } else if constexpr (RULE == MF_RULE_SWEEP) {
+    // colour class of the node; the others are copied unchanged
+    // neighbours always differ in colour: (x + y) mod 2 with 4 neighbours,
+    // (x mod 2) + 2 (y mod 2) with 8
+    const int colour = CONN == 4 ? ((x + y) & 1) : ((x & 1) + 2 * (y & 1));
+    if (colour == rx.colour) {
+#pragma unroll
+      for (int j = 0; j < LG; ++j) z[j] = valid[j] ? -mm[j] : -INFINITY;
+      store_normalised<LG>(out, valid, z, N, n);
+    } else {
+#pragma unroll
+      for (int j = 0; j < LG; ++j)
+        if (valid[j]) out[(unsigned)j * N + n] = ell[j];
+    }
+  } else {
+    static_assert(RULE == MF_RULE_MOMENTUM || RULE == MF_RULE_ADAM, "unknown step rule");
+    float* __restrict__ mom = rx.mom + base;
+    if (rx.init) {
+      // mom^0 = m(q^0), v^0 = v0; log q is left as it is
+#pragma unroll
+      for (int j = 0; j < LG; ++j) {
+        if (valid[j]) {
+          mom[(unsigned)j * N + n] = mm[j];
+          if constexpr (RULE == MF_RULE_ADAM) rx.sq[base + (unsigned)j * N + n] = rx.v0;
+        }
+      }
+      return;
+    }
+    float mo[LG];
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      const unsigned o = (unsigned)(j < L ? j : L - 1) * N + n;
+      mo[j] = rx.gamma1 * mom[o] + (1.0f - rx.gamma1) * mm[j];
+    }
+    if constexpr (RULE == MF_RULE_MOMENTUM) {
+      const float om = 1.0f - a.alpha;
+#pragma unroll
+      for (int j = 0; j < LG; ++j) z[j] = valid[j] ? om * ell[j] - a.alpha * mo[j] : -INFINITY;
+    } else {
+      // natural gradient g = m + log q, centred over the labels
+      float* __restrict__ sq = rx.sq + base;
+      float g[LG];
+      float gbar = 0.f;
+#pragma unroll
+      for (int j = 0; j < LG; ++j) {
+        g[j] = mm[j] + ell[j];
+        if (valid[j]) gbar += g[j];
+      }
+      gbar /= (float)L;
+#pragma unroll
+      for (int j = 0; j < LG; ++j) {
+        const unsigned o = (unsigned)(j < L ? j : L - 1) * N + n;
+        const float gc = g[j] - gbar;
+        const float v = rx.gamma2 * sq[o] + (1.0f - rx.gamma2) * gc * gc;
+        const float dt = fmaxf(sqrtf(v) * rx.d + rx.eps - 1.0f, 1e-6f);
+        const float eta = 1.0f / (1.0f + dt);
+        z[j] = valid[j] ? (1.0f - eta) * ell[j] - eta * mo[j] : -INFINITY;
+        if (valid[j]) sq[o] = v;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < LG; ++j)
+      if (valid[j]) mom[(unsigned)j * N + n] = mo[j];
+    store_normalised<LG>(out, valid, z, N, n);
+  }
+}
+
 // Branch-free tile body.  LC is the label count when it is known at compile
 // time (0: runtime a.L); slots l >= L are carried with q = 0 and a zero row
 // and column of Theta, so every lane runs the same straight-line code and
 // only the final store is masked.
-template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY>
+//
+// RULE selects the update made from the messages m (mf_rule); every rule but
+// MF_RULE_FIXED runs one lane per node and takes its extra state and
+// constants from rx.
+template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY, int RULE = MF_RULE_FIXED>
 __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b, int x0, int y0,
-                                 Smem<LG, LPN, TX, TY, PREC>& sm) {
+                                 Smem<LG, LPN, TX, TY, PREC>& sm, const RuleArgs* rx = nullptr) {
+  static_assert(RULE == MF_RULE_FIXED || LPN == 1, "step rules run one lane per node");
   using G = Geometry<LG, LPN, TX, TY>;
   using M = MsgT<PREC>;
   constexpr int LP = G::LP, PS = G::PS, LS = G::LS, HX = G::HX, NT = G::NT, HALO = G::HALO;
@@ -191,7 +313,8 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
     S[j] = s;
   }
 
-  float z[LG];
+  // m = u + Theta S (Potts: u + w (sum(S) 1 - S)) and the fixed-step z
+  float mm[LG], z[LG];
   if (COMPAT == MF_COMPAT_POTTS) {
     float tot = 0.f;
 #pragma unroll
@@ -200,6 +323,7 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
 #pragma unroll
     for (int j = 0; j < LG; ++j) {
       const float m = uu[j] + a.potts_w * (tot - S[j]);
+      mm[j] = m;
       z[j] = valid[j] ? one_minus_alpha * ell[j] - a.alpha * m : -INFINITY;
     }
   } else {
@@ -220,9 +344,15 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
       float acc = 0.f;
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) acc = fmaf(th[k], Sa[k], acc);
-      const float zz = one_minus_alpha * ell[j] - a.alpha * (uu[j] + acc);
+      const float m = uu[j] + acc;
+      mm[j] = m;
+      const float zz = one_minus_alpha * ell[j] - a.alpha * m;
       z[j] = valid[j] ? zz : -INFINITY;
     }
+  }
+  if constexpr (RULE != MF_RULE_FIXED) {
+    rule_epilogue<LG, CONN, RULE>(a, *rx, valid, ell, mm, z, base, N, n, x, y, L);
+    return;
   }
 
   float mx = z[0];

@@ -69,6 +69,12 @@ mf::WorkspaceLayout layout_for(const mf_desc& d) {
     w.dqd = off;
     off += align256(sizeof(double) * B * (size_t)d.n_nodes * (size_t)d.n_labels);
   }
+  if (d.rule == MF_RULE_MOMENTUM || d.rule == MF_RULE_ADAM) {
+    // momentum average (and ADAM second moment) [B][L][N], kept across steps
+    const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
+    w.rule_state = off;
+    off += align256(sizeof(float) * E * (d.rule == MF_RULE_ADAM ? 2 : 1));
+  }
   w.total = off;
   return w;
 }
@@ -86,6 +92,15 @@ mf_status check_desc(const mf_desc* d, std::string* msg) {
   if (d->compat != MF_COMPAT_GENERAL && d->compat != MF_COMPAT_POTTS) return bad("unknown compat kind");
   if (d->precision < MF_P_F32 || d->precision > MF_P_F16MSG) return bad("unknown precision");
   if (d->init < MF_INIT_UNARY || d->init > MF_INIT_STATE) return bad("unknown init mode");
+  if (d->rule < MF_RULE_FIXED || d->rule > MF_RULE_SWEEP) return bad("unknown step rule");
+  if (d->rule == MF_RULE_MOMENTUM || d->rule == MF_RULE_ADAM) {
+    if (!(d->rule_gamma1 >= 0.f && d->rule_gamma1 < 1.f)) return bad("rule_gamma1 must lie in [0, 1)");
+  }
+  if (d->rule == MF_RULE_ADAM) {
+    if (!(d->rule_gamma2 >= 0.f && d->rule_gamma2 < 1.f)) return bad("rule_gamma2 must lie in [0, 1)");
+    if (!(d->rule_eps >= 0.f && std::isfinite(d->rule_eps))) return bad("rule_eps must be finite and >= 0");
+    if (!(d->rule_v0 >= 0.f && std::isfinite(d->rule_v0))) return bad("rule_v0 must be finite and >= 0");
+  }
   if (!std::isfinite(d->potts_w)) return bad("potts_w must be finite");
   if (is_grid(d->graph)) {
     if (d->height < 1 || d->width < 1) return bad("grid height and width must be >= 1");
@@ -107,6 +122,17 @@ mf_status check_desc(const mf_desc* d, std::string* msg) {
   if (d->n_labels > MF_MAX_LABELS) {
     *msg = "n_labels above MF_MAX_LABELS";
     return MF_EUNSUPPORTED;
+  }
+  if (d->rule != MF_RULE_FIXED) {
+    if (!is_grid(d->graph)) {
+      *msg = "step rules other than MF_RULE_FIXED are implemented for grids";
+      return MF_EUNSUPPORTED;
+    }
+    if (d->precision != MF_P_F32) {
+      *msg = "step rules other than MF_RULE_FIXED run with FP32 messages";
+      return MF_EUNSUPPORTED;
+    }
+    if (d->rule == MF_RULE_ADAPTIVE && d->n_labels != 2) return bad("MF_RULE_ADAPTIVE needs n_labels == 2");
   }
   if ((size_t)d->n_labels * (size_t)d->n_nodes >= MF_MAX_LABEL_NODES) {
     *msg = "n_labels * n_nodes must be below MF_MAX_LABEL_NODES per problem";
@@ -181,6 +207,42 @@ float* csr_q(const mf_handle* h, int which) {
   return (float*)((char*)h->d.workspace + h->ws.csr_q) + (size_t)which * elems;
 }
 
+mf::StepArgs grid_args(const mf_handle* h, int from) {
+  const mf_desc& d = h->d;
+  mf::StepArgs a;
+  a.unary = d.unary;
+  a.state_in = buf(h, from);
+  a.state_out = buf(h, from ^ 1);
+  a.theta = d.theta;
+  a.B = d.batch;
+  a.L = d.n_labels;
+  a.N = d.n_nodes;
+  a.H = d.height;
+  a.W = d.width;
+  a.alpha = (float)d.alpha;
+  a.potts_w = d.potts_w;
+  return a;
+}
+
+mf::RuleArgs rule_args(const mf_handle* h, int init, int colour) {
+  const mf_desc& d = h->d;
+  const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
+  mf::RuleArgs r;
+  float* st = (d.rule == MF_RULE_MOMENTUM || d.rule == MF_RULE_ADAM)
+                  ? (float*)((char*)d.workspace + h->ws.rule_state)
+                  : nullptr;
+  r.mom = st;
+  r.sq = (st && d.rule == MF_RULE_ADAM) ? st + E : nullptr;
+  r.gamma1 = d.rule_gamma1;
+  r.gamma2 = d.rule_gamma2;
+  r.eps = d.rule_eps;
+  r.v0 = d.rule_v0;
+  r.d = (float)(1.0 / d.alpha - 1.0);
+  r.init = init;
+  r.colour = colour;
+  return r;
+}
+
 mf_status enqueue_init(mf_handle* h) {
   const mf_desc& d = h->d;
   hipError_t e = mf::launch_clear_flags(flags_ptr(h), 64, h->stream);
@@ -202,6 +264,12 @@ mf_status enqueue_init(mf_handle* h) {
     e = mf::launch_dense_prepare(a, h->ws.dense_ns, h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("dense prepare launch: ") + hipGetErrorString(e));
   }
+  if (d.rule == MF_RULE_MOMENTUM || d.rule == MF_RULE_ADAM) {
+    // momentum average m(q^0) (and the ADAM second moment v0); log q untouched
+    e = mf::launch_grid_rule_step(grid_args(h, 0), rule_args(h, 1, 0), d.graph == MF_GRID4 ? 4 : 8, d.compat,
+                                  d.rule, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("rule state init: ") + hipGetErrorString(e));
+  }
   h->cur = 0;
   h->iter = 0;
   return MF_OK;
@@ -215,7 +283,7 @@ mf_status enqueue_init(mf_handle* h) {
 // per compute unit (three measured faster than two or four).  Larger grids
 // stream HBM at one step per launch.
 int choose_steps_per_launch(const mf_desc& d) {
-  if (!is_grid(d.graph)) return 1;
+  if (!is_grid(d.graph) || d.rule != MF_RULE_FIXED) return 1;
   const int kmax = mf::grid_max_steps_per_launch(d.n_labels, d.compat, d.precision);
   int k = d.steps_per_launch;
   if (k <= 0) {
@@ -265,10 +333,30 @@ mf_status enqueue_dense_steps(mf_handle* h, int n) {
   return MF_OK;
 }
 
+// Non-fixed step rules: one launch per step; a SWEEP step is one launch per
+// colour class, each writing every node (new values for its colour, copies
+// for the others) to the other buffer.
+mf_status enqueue_rule_steps(mf_handle* h, int n) {
+  const mf_desc& d = h->d;
+  const int conn = d.graph == MF_GRID4 ? 4 : 8;
+  const int launches = d.rule == MF_RULE_SWEEP ? (conn == 4 ? 2 : 4) : 1;
+  for (; n > 0; --n) {
+    for (int c = 0; c < launches; ++c) {
+      hipError_t e = mf::launch_grid_rule_step(grid_args(h, h->cur), rule_args(h, 0, c), conn, d.compat, d.rule,
+                                               h->stream);
+      if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("rule step launch: ") + hipGetErrorString(e));
+      h->cur ^= 1;
+    }
+    h->iter += 1;
+  }
+  return MF_OK;
+}
+
 mf_status enqueue_steps(mf_handle* h, int n) {
   const mf_desc& d = h->d;
   if (d.graph == MF_CSR) return enqueue_csr_steps(h, n);
   if (d.graph == MF_DENSE) return enqueue_dense_steps(h, n);
+  if (d.rule != MF_RULE_FIXED) return enqueue_rule_steps(h, n);
   while (n > 0) {
     const int ks = n < h->k_launch ? n : h->k_launch;
     mf::StepArgs a;
@@ -457,6 +545,8 @@ mf_status mf_step_many(mf_handle* const* hs, int32_t count, int32_t n_steps) {
   for (int i = 0; i < count; ++i) {
     if (!hs[i]) return fail(nullptr, MF_EINVAL, "NULL handle in hs");
     if (!is_grid(hs[i]->d.graph)) return fail(hs[i], MF_EUNSUPPORTED, "mf_step_many batches grid problems");
+    if (hs[i]->d.rule != MF_RULE_FIXED)
+      return fail(hs[i], MF_EUNSUPPORTED, "mf_step_many batches the fixed-step rule");
     if (hs[i]->stream != hs[0]->stream) return fail(hs[i], MF_EINVAL, "handles use different streams");
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[i], MF_EINVAL, "handle listed twice");
@@ -514,7 +604,7 @@ mf_status mf_step_many(mf_handle* const* hs, int32_t count, int32_t n_steps) {
 }
 
 size_t mf_backward_workspace_size(const mf_handle* h, int32_t ckpt_every) {
-  if (!h || ckpt_every < 1 || !is_grid(h->d.graph)) return 0;
+  if (!h || ckpt_every < 1 || !is_grid(h->d.graph) || h->d.rule != MF_RULE_FIXED) return 0;
   const mf_desc& d = h->d;
   const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
   const size_t LL = (size_t)d.n_labels * d.n_labels;
@@ -533,6 +623,7 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
   if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
   const mf_desc& d = h->d;
   if (!is_grid(d.graph)) return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for grids");
+  if (d.rule != MF_RULE_FIXED) return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for the fixed-step rule");
   if (T < 0 || ckpt_every < 1) return fail(h, MF_EINVAL, "need T >= 0 and ckpt_every >= 1");
   if (!ckpt_states || !grad_logq_T || !grad_unary || !grad_theta || !work)
     return fail(h, MF_EINVAL, "NULL argument");

@@ -92,6 +92,16 @@ struct DenseStepArgs {
   float alpha, potts_w, inv_n;
 };
 
+// Step rules other than the fixed proximal step (grid_rules.hip).
+struct RuleArgs {
+  float* mom;              // [B][L][N] momentum average (MOMENTUM, ADAM)
+  float* sq;               // [B][L][N] second moment (ADAM)
+  float gamma1, gamma2, eps, v0;
+  float d;                 // 1 / alpha - 1
+  int init;                // 1: write the rule state of q^0 (mom = m, sq = v0) only
+  int colour;              // SWEEP: the colour class this launch updates
+};
+
 // Power method for the tangent-space Lipschitz constant (lipschitz_kernels.hip).
 struct LipArgs {
   const float* v;          // [L][N] current iterate, before its scale
@@ -153,6 +163,7 @@ struct WorkspaceLayout {
   size_t dt = 0;           // float[2][B][NRB][32] column sums
   size_t dc = 0;           // int[B][NRB] counters
   size_t dqd = 0;          // double[B][N][L] free-energy scratch
+  size_t rule_state = 0;   // float[1 or 2][B][L][N] momentum / ADAM state
   DenseGeometry dg;
   int dense_ns = 0;
   size_t total = 0;
@@ -173,6 +184,9 @@ hipError_t launch_lip_center(const LipArgs& a, const float* v0, hipStream_t s);
 hipError_t launch_lip_hvp(const LipArgs& a, hipStream_t s);
 hipError_t launch_lip_reduce(const LipArgs& a, int n_blocks, int mode, hipStream_t s);
 int lip_blocks(int graph, int N, int H, int W);
+// One step of a non-fixed rule on a grid (FP32 messages, one step per launch).
+hipError_t launch_grid_rule_step(const StepArgs& a, const RuleArgs& r, int conn, int compat, int rule,
+                                 hipStream_t s);
 hipError_t launch_exp(const float* state, float* q, size_t count, hipStream_t s);
 hipError_t launch_dense_kernel(const float* f, int n, int dim, uint16_t* K, hipStream_t s);
 int dense_planes(int precision);

@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")
 
-MF_ABI_VERSION = 1
+MF_ABI_VERSION = 2
 MF_MAX_LABELS = 32
 
 MF_OK, MF_EINVAL, MF_ENONFINITE, MF_EDEVICE, MF_EUNSUPPORTED, MF_ENOWORKSPACE = 0, -1, -2, -3, -4, -5
@@ -28,6 +28,7 @@ GRID4, GRID8, CSR, DENSE = 0, 1, 2, 3
 COMPAT_GENERAL, COMPAT_POTTS = 0, 1
 PRECISIONS = {"f32": 0, "bf16": 1, "f16": 2}
 INIT_MODES = {"unary": 0, "uniform": 1, "state": 2}
+RULES = {"fixed": 0, "adaptive": 1, "adhoc": 2, "momentum": 3, "adam": 4, "sweep": 5}
 
 
 class MFError(RuntimeError):
@@ -43,6 +44,8 @@ class MFDesc(ctypes.Structure):
         ("graph", ctypes.c_int32), ("compat", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("init", ctypes.c_int32), ("alpha", ctypes.c_double), ("potts_w", ctypes.c_float),
         ("steps_per_launch", ctypes.c_int32),
+        ("rule", ctypes.c_int32), ("rule_gamma1", ctypes.c_float), ("rule_gamma2", ctypes.c_float),
+        ("rule_eps", ctypes.c_float), ("rule_v0", ctypes.c_float),
         ("csr_row_ptr", ctypes.c_void_p), ("csr_col", ctypes.c_void_p), ("csr_w", ctypes.c_void_p),
         ("csr_nnz", ctypes.c_int64),
         ("dense_K", ctypes.c_void_p), ("cooc", ctypes.c_void_p),
@@ -176,7 +179,9 @@ class MeanField:
                  csr_row_ptr: Optional[torch.Tensor] = None, csr_col: Optional[torch.Tensor] = None,
                  csr_w: Optional[torch.Tensor] = None, dense_K: Optional[torch.Tensor] = None,
                  cooc: Optional[torch.Tensor] = None, state: Optional[torch.Tensor] = None,
-                 stream: Optional[torch.cuda.Stream] = None, steps_per_launch: int = 0):
+                 stream: Optional[torch.cuda.Stream] = None, steps_per_launch: int = 0,
+                 rule: str = "fixed", gamma1: Optional[float] = None, gamma2: float = 0.999,
+                 eps: float = 1e-8, v0: float = 1.0):
         L_ = lib()
         self._handle = None
         u = _dev_tensor(unary, torch.float32, "unary", None)
@@ -214,6 +219,12 @@ class MeanField:
         d.alpha = float(alpha)
         d.potts_w = 0.0 if potts_w is None else float(potts_w)
         d.steps_per_launch = int(steps_per_launch)
+        if rule not in RULES:
+            raise ValueError(f"unknown step rule {rule!r}")
+        d.rule = RULES[rule]
+        # momentum decay: 0.95 for OURS-MOMENTUM and 0.9 for OURS-ADAM (Sec. 4.1)
+        d.rule_gamma1 = float(gamma1 if gamma1 is not None else (0.9 if rule == "adam" else 0.95))
+        d.rule_gamma2, d.rule_eps, d.rule_v0 = float(gamma2), float(eps), float(v0)
         d.csr_row_ptr, d.csr_col, d.csr_w = (_ptr(t) for t in self.csr)
         d.csr_nnz = 0 if self.csr[1] is None else self.csr[1].numel()
         d.dense_K = _ptr(self.dense_K)

@@ -192,3 +192,32 @@ def test_admissible_alpha_rule():
     assert mf.admissible_alpha(float("nan")) == 1.0
     assert abs(mf.admissible_alpha(3.981888) - 1 / (1 + 1.01 * 3.981888)) < 1e-15
     assert abs(mf.admissible_alpha(2.0, 0.5) - 1 / 3) < 1e-15     # margin below 1 taken as 1
+
+
+def test_step_rule_validation():
+    """Rules other than the fixed step: grids with FP32 messages; ADAPTIVE needs
+    L = 2; the decays lie in [0, 1); momentum and ADAM state sits in the workspace."""
+    assert validate(good_desc(rule=9)) == mf.MF_EINVAL
+    assert validate(good_desc(rule=mf.RULES["adaptive"])) == mf.MF_EINVAL            # L = 21
+    assert validate(good_desc(rule=mf.RULES["adaptive"], n_labels=2)) == mf.MF_OK
+    assert validate(good_desc(rule=mf.RULES["adhoc"], precision=1)) == mf.MF_EUNSUPPORTED
+    assert validate(good_desc(rule=mf.RULES["momentum"], rule_gamma1=1.0)) == mf.MF_EINVAL
+    assert validate(good_desc(rule=mf.RULES["momentum"], rule_gamma1=0.95)) == mf.MF_OK
+    adam = dict(rule=mf.RULES["adam"], rule_gamma1=0.9, rule_gamma2=0.999, rule_eps=1e-8, rule_v0=1.0)
+    assert validate(good_desc(**adam)) == mf.MF_OK
+    assert validate(good_desc(**{**adam, "rule_gamma2": -0.1})) == mf.MF_EINVAL
+    assert validate(good_desc(**{**adam, "rule_eps": float("inf")})) == mf.MF_EINVAL
+    assert validate(good_desc(**{**adam, "rule_v0": -1.0})) == mf.MF_EINVAL
+    assert validate(good_desc(rule=mf.RULES["sweep"])) == mf.MF_OK
+    E = 64 * 64 * 21 * 4
+    base = mf.lib().mf_workspace_size(ctypes.byref(good_desc()))
+    mom = mf.lib().mf_workspace_size(ctypes.byref(good_desc(rule=mf.RULES["momentum"], rule_gamma1=0.95)))
+    ad = mf.lib().mf_workspace_size(ctypes.byref(good_desc(**adam)))
+    assert mom >= base + E and ad >= base + 2 * E
+
+
+def test_step_rules_need_a_grid():
+    rp = FAKE + (1 << 35)
+    d = good_desc(graph=mf.CSR, height=0, width=0, csr_row_ptr=rp, csr_col=rp + 4096, csr_nnz=8,
+                  rule=mf.RULES["adhoc"])
+    assert validate(d) == mf.MF_EUNSUPPORTED
