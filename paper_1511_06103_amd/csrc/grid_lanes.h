@@ -372,11 +372,30 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
   }
 }
 
+// Workgroups are dealt to the eight XCDs round-robin (workgroup w runs on
+// XCD w mod 8), and each XCD has its own L2.  Tile t = (x, y, b) in
+// row-major order is given to workgroup w so that XCD k takes the k-th
+// contiguous run of tiles: horizontally and vertically adjacent tiles then
+// share an L2, and the halo rows and the cache lines of the side halo
+// columns that a tile reads are the lines its neighbours read.
+constexpr int kXcds = 8;
+
+__device__ inline int xcd_tile(int w, int total) {
+  const int q = total / kXcds, r = total - q * kXcds;
+  const int x = w % kXcds;
+  return x * q + (x < r ? x : r) + w / kXcds;
+}
+
 template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY>
 __global__ __launch_bounds__(TX * TY * LPN) void step_kernel(StepArgs a, float one_minus_alpha) {
   __shared__ Smem<LG, LPN, TX, TY, PREC> sm;
-  tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY>(a, one_minus_alpha, blockIdx.z, blockIdx.x * TX,
-                                                        blockIdx.y * TY, sm);
+  const int tiles_x = (a.W + TX - 1) / TX, tiles_y = (a.H + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, tiles_x * tiles_y * a.B);
+  const int per_item = tiles_x * tiles_y;
+  const int b = t / per_item;
+  const int r = t - b * per_item;
+  const int ty = r / tiles_x, tx = r - ty * tiles_x;
+  tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY>(a, one_minus_alpha, b, tx * TX, ty * TY, sm);
 }
 
 // Many independent problems in one launch: slot k owns workgroups
@@ -423,7 +442,8 @@ template <int PREC>
 struct ForPrec {
   template <int LG, int LPN, int LC, int TX, int TY>
   static hipError_t one(const StepArgs& a, int conn, int compat, hipStream_t s) {
-    dim3 grid((a.W + TX - 1) / TX, (a.H + TY - 1) / TY, a.B);
+    // one-dimensional grid: step_kernel maps workgroups to tiles XCD by XCD
+    dim3 grid(((a.W + TX - 1) / TX) * ((a.H + TY - 1) / TY) * a.B);
     dim3 block(TX * TY * LPN);
     const float om = (float)(1.0 - (double)a.alpha);
     if (conn == 4) {

@@ -314,8 +314,14 @@ __global__ __launch_bounds__((MGeom<LG, LC, PREC, TX, TY, K>::NT)) void multi_st
   const int L = LC > 0 ? LC : a.L;
   const unsigned N = (unsigned)a.N;
   const int H = a.H, W = a.W;
-  const int b = blockIdx.z;
-  const int gx0 = blockIdx.x * TX - K, gy0 = blockIdx.y * TY - K;
+  // tiles dealt XCD by XCD (see lanes::xcd_tile): adjacent tiles, whose
+  // K-halo regions overlap, share an L2
+  const int tiles_x = (a.W + TX - 1) / TX, tiles_y = (a.H + TY - 1) / TY;
+  const int tile = lanes::xcd_tile(blockIdx.x, tiles_x * tiles_y * a.B);
+  const int b = tile / (tiles_x * tiles_y);
+  const int tr = tile - b * (tiles_x * tiles_y);
+  const int tyi = tr / tiles_x, txi = tr - tyi * tiles_x;
+  const int gx0 = txi * TX - K, gy0 = tyi * TY - K;
   const size_t base = (size_t)b * L * N;
   const float* __restrict__ lin = a.state_in + base;
   const float* __restrict__ ug = a.unary + base;
@@ -591,7 +597,7 @@ struct ForPrec {
   }
   template <int LG, int LC, int CONN, int K>
   static hipError_t go_mfma(const StepArgs& a, int ks, hipStream_t s) {
-    dim3 grid((a.W + 15) / 16, (a.H + 15) / 16, a.B);
+    dim3 grid(((a.W + 15) / 16) * ((a.H + 15) / 16) * a.B);
     const float om = (float)(1.0 - (double)a.alpha);
     hipLaunchKernelGGL((multi_step_mfma_kernel<LG, LC, CONN, PREC, 16, 16, K>), grid,
                        dim3(MGeom<LG, LC, PREC, 16, 16, K>::NT), 0, s, a, om, ks);

@@ -275,13 +275,13 @@ mf_status enqueue_init(mf_handle* h) {
   return MF_OK;
 }
 
-// Steps per launch: small grids are bound by launch and memory latency, so
-// several steps are fused.  Where Theta S runs on the matrix cores (general
-// Theta, 8 < L <= 32) four steps are fused below sixteen 64 x 4 tiles per
-// compute unit (measured: 256 x 256 and 16 x 128 x 128 at L = 21 are fastest
-// at four, 2048 x 2048 at one); the VALU kernel fuses three below four tiles
-// per compute unit (three measured faster than two or four).  Larger grids
-// stream HBM at one step per launch.
+// Steps per launch: small grids (fewer 64 x 4 tiles than four per compute
+// unit) are bound by launch and memory latency, so several steps are fused:
+// four where Theta S runs on the matrix cores (general Theta, 8 < L <= 32;
+// measured fastest on the 256 x 256, L = 21 grid), otherwise three (three
+// measured faster than two or four for the VALU kernel).  Larger grids
+// stream HBM at one step per launch (16 x 128 x 128 and 2048 x 2048 at
+// L = 21 measured fastest at one).
 int choose_steps_per_launch(const mf_desc& d) {
   if (!is_grid(d.graph) || d.rule != MF_RULE_FIXED) return 1;
   const int kmax = mf::grid_max_steps_per_launch(d.n_labels, d.compat, d.precision);
@@ -290,7 +290,7 @@ int choose_steps_per_launch(const mf_desc& d) {
     const int64_t tiles = (int64_t)d.batch * ((d.width + mf::kTileX - 1) / mf::kTileX) *
                           ((d.height + mf::kTileY - 1) / mf::kTileY);
     const bool mfma = d.compat == MF_COMPAT_GENERAL && d.n_labels > 8 && d.n_labels <= 32;
-    k = mfma ? (tiles >= 16 * 256 ? 1 : 4) : (tiles >= 4 * 256 ? 1 : 3);
+    k = tiles >= 4 * 256 ? 1 : (mfma ? 4 : 3);
   }
   return k < kmax ? k : kmax;
 }
