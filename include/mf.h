@@ -203,7 +203,10 @@ mf_status mf_free_energy(mf_handle *h, double *F_host);
 mf_status mf_marginals(mf_handle *h, float *q_out);
 
 /* Synchronise the stream and report deferred device errors:
- * MF_ENONFINITE if a non-finite unary was seen, MF_EDEVICE on a HIP error. */
+ * MF_ENONFINITE if a non-finite unary (or initial state) was seen, MF_EINVAL
+ * for malformed CSR arrays, MF_EDEVICE on a HIP error.  The conditions
+ * accumulate over the initialisations since the handle was created or
+ * since the last mf_check that reported one; reporting clears them. */
 mf_status mf_check(mf_handle *h);
 
 /* Device pointer to the current log q, [B][L][N] inside desc.state. */

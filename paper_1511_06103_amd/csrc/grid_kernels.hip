@@ -12,30 +12,51 @@ namespace {
 
 // Initial log q per node: -u - lse(-u) (mode 0) or -log L (mode 1); mode 2
 // only checks the caller's state.  Sets flags[0] on a non-finite input.
-__global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ unary,
-                                                   float* __restrict__ state, int L, int N,
-                                                   int mode, int* __restrict__ flags) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+// log q^0 per node (Eq. 6 reading): -u - lse(-u) (mode 0), uniform (mode 1),
+// or the caller's state, checked (mode 2).  LC label slots (the label count
+// rounded up to 2, 4, 8, 16, 21 or 32) hold the node's values in registers:
+// the unaries are read once.
+template <int LC>
+__global__ __launch_bounds__(64) void init_kernel(const float* __restrict__ unary, float* __restrict__ state,
+                                                  int L, int N, int mode, int* __restrict__ flags) {
+  const int n = blockIdx.x * 64 + threadIdx.x;
   const int b = blockIdx.y;
   if (n >= N) return;
   const size_t base = (size_t)b * L * N + n;
   bool bad = false;
-  float mx = -INFINITY;
-  for (int l = 0; l < L; ++l) {
-    const float v = unary[base + (size_t)l * N];
-    bad |= !isfinite(v);
-    mx = fmaxf(mx, -v);
-  }
   if (mode == 0) {
+    float v[LC];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int l = 0; l < LC; ++l) {
+      v[l] = l < L ? -unary[base + (size_t)l * N] : -INFINITY;
+      if (l < L) bad |= !isfinite(v[l]);
+      mx = fmaxf(mx, v[l]);
+    }
     float se = 0.f;
-    for (int l = 0; l < L; ++l) se += expf(-unary[base + (size_t)l * N] - mx);
+#pragma unroll
+    for (int l = 0; l < LC; ++l) se += l < L ? expf(v[l] - mx) : 0.f;
     const float lse = mx + logf(se);
-    for (int l = 0; l < L; ++l) state[base + (size_t)l * N] = -unary[base + (size_t)l * N] - lse;
+#pragma unroll
+    for (int l = 0; l < LC; ++l)
+      if (l < L) state[base + (size_t)l * N] = v[l] - lse;
   } else if (mode == 1) {
-    const float v = -logf((float)L);
-    for (int l = 0; l < L; ++l) state[base + (size_t)l * N] = v;
+    const float u0 = -logf((float)L);
+#pragma unroll
+    for (int l = 0; l < LC; ++l) {
+      if (l < L) {
+        bad |= !isfinite(unary[base + (size_t)l * N]);
+        state[base + (size_t)l * N] = u0;
+      }
+    }
   } else {
-    for (int l = 0; l < L; ++l) bad |= !isfinite(state[base + (size_t)l * N]);
+#pragma unroll
+    for (int l = 0; l < LC; ++l) {
+      if (l < L) {
+        bad |= !isfinite(unary[base + (size_t)l * N]);
+        bad |= !isfinite(state[base + (size_t)l * N]);
+      }
+    }
   }
   if (bad) atomicOr(flags, 1);
 }
@@ -48,6 +69,16 @@ __global__ __launch_bounds__(256) void exp_kernel(const float* __restrict__ s, f
                                                   size_t count) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) q[i] = expf(s[i]);
+}
+
+// Four elements per thread (both pointers 16-byte aligned, count % 4 == 0).
+__global__ __launch_bounds__(256) void exp4_kernel(const float4* __restrict__ s, float4* __restrict__ q,
+                                                   size_t count4) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count4) {
+    const float4 v = s[i];
+    q[i] = make_float4(expf(v.x), expf(v.y), expf(v.z), expf(v.w));
+  }
 }
 
 __device__ inline double wave_sum(double v) {
@@ -136,8 +167,13 @@ int grid_blocks_per_item(int H, int W) { return (H * W + 255) / 256; }
 
 hipError_t launch_init(const float* unary, float* state, int B, int L, int N, int mode, int* flags,
                        hipStream_t s) {
-  dim3 grid((N + 255) / 256, B);
-  hipLaunchKernelGGL(init_kernel, grid, dim3(256), 0, s, unary, state, L, N, mode, flags);
+  const dim3 grid((N + 63) / 64, B), block(64);
+  if (L <= 2) hipLaunchKernelGGL(init_kernel<2>, grid, block, 0, s, unary, state, L, N, mode, flags);
+  else if (L <= 4) hipLaunchKernelGGL(init_kernel<4>, grid, block, 0, s, unary, state, L, N, mode, flags);
+  else if (L <= 8) hipLaunchKernelGGL(init_kernel<8>, grid, block, 0, s, unary, state, L, N, mode, flags);
+  else if (L <= 16) hipLaunchKernelGGL(init_kernel<16>, grid, block, 0, s, unary, state, L, N, mode, flags);
+  else if (L == 21) hipLaunchKernelGGL(init_kernel<21>, grid, block, 0, s, unary, state, L, N, mode, flags);
+  else hipLaunchKernelGGL(init_kernel<MF_MAX_LABELS>, grid, block, 0, s, unary, state, L, N, mode, flags);
   return hipGetLastError();
 }
 
@@ -148,7 +184,13 @@ hipError_t launch_clear_flags(int* flags, int n, hipStream_t s) {
 
 hipError_t launch_exp(const float* state, float* q, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(exp_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, state, q, count);
+  if (count % 4 == 0 && ((uintptr_t)state & 15u) == 0 && ((uintptr_t)q & 15u) == 0) {
+    const size_t c4 = count / 4;
+    hipLaunchKernelGGL(exp4_kernel, dim3((unsigned)((c4 + 255) / 256)), dim3(256), 0, s, (const float4*)state,
+                       (float4*)q, c4);
+  } else {
+    hipLaunchKernelGGL(exp_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, state, q, count);
+  }
   return hipGetLastError();
 }
 

@@ -243,10 +243,15 @@ mf::RuleArgs rule_args(const mf_handle* h, int init, int colour) {
   return r;
 }
 
-mf_status enqueue_init(mf_handle* h) {
+// The flags are cleared when the handle is created and by the mf_check that
+// reports them, so a solve does not spend a launch on it.
+mf_status enqueue_init(mf_handle* h, bool clear_flags) {
   const mf_desc& d = h->d;
-  hipError_t e = mf::launch_clear_flags(flags_ptr(h), 64, h->stream);
-  if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
+  hipError_t e = hipSuccess;
+  if (clear_flags) {
+    e = mf::launch_clear_flags(flags_ptr(h), 64, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
+  }
   if (d.graph == MF_CSR) {
     e = mf::launch_csr_check(d.csr_row_ptr, d.csr_col, d.n_nodes, d.csr_nnz, flags_ptr(h), h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("CSR check launch: ") + hipGetErrorString(e));
@@ -415,7 +420,7 @@ mf_status mf_init(const mf_desc* d, mf_handle** out) {
   h->stream = (hipStream_t)d->stream;
   h->ws = layout_for(*d);
   h->k_launch = choose_steps_per_launch(*d);
-  const mf_status s2 = enqueue_init(h);
+  const mf_status s2 = enqueue_init(h, true);
   if (s2 != MF_OK) {
     g_err = h->err;
     delete h;
@@ -435,7 +440,7 @@ mf_status mf_solve(mf_handle* h, int32_t iters, float* q_out) {
   if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
   if (iters < 0) return fail(h, MF_EINVAL, "iters must be >= 0");
   if (((uintptr_t)q_out) & 3u) return fail(h, MF_EINVAL, "q_out must be 4-byte aligned");
-  mf_status st = enqueue_init(h);
+  mf_status st = enqueue_init(h, false);
   if (st != MF_OK) return st;
   st = enqueue_steps(h, iters);
   if (st != MF_OK) return st;
@@ -522,6 +527,11 @@ mf_status mf_check(mf_handle* h) {
   hipError_t e = hipMemcpyAsync(&flag, flags_ptr(h), sizeof(int), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("device error: ") + hipGetErrorString(e));
+  if (flag != 0) {
+    // reported once: clear for the checks that follow
+    e = mf::launch_clear_flags(flags_ptr(h), 64, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
+  }
   if (flag & 2) return fail(h, MF_EINVAL, "malformed CSR arrays (row_ptr not monotone from 0 to nnz, "
                                          "or a column index out of range)");
   if (flag & 1) return fail(h, MF_ENONFINITE, "non-finite unary or initial state");
