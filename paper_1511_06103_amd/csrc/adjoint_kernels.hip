@@ -10,8 +10,8 @@
 // Kernel A does everything up to Sb for one 64 x 4 tile (S needs the q halo),
 // kernel B the transposed stencil over Sb (needs the Sb halo) and the new g.
 // Theta_bar partials are per tile: mb and S of the tile's nodes are staged in
-// LDS and the L x L block product is formed there, then reduced over tiles in
-// a fixed order into an FP64 accumulator.
+// LDS and the L x L block product is formed there on the FP32 matrix cores,
+// then reduced over tiles in a fixed order into an FP64 accumulator.
 #include <hip/hip_runtime.h>
 
 #include "mf_internal.h"
@@ -22,12 +22,22 @@ namespace {
 constexpr int AX = kTileX + 2;
 constexpr int AY = kTileY + 2;
 constexpr int AN = AX * AY;
+// Row stride of the m_bar / S staging in LDS: 4 words past the 256 nodes, so
+// that the 16 label rows a wavefront reads at once fall on distinct banks.
+constexpr int RS = kThreads + 4;
+// Tile partials of Theta_bar summed per stage-1 block.
+constexpr int kThetaChunk = 32;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int LP, bool EXACT, int CONN, int COMPAT>
 __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
+  constexpr int NB = (LP + 15) / 16;       // 16-label blocks of Theta_bar
   __shared__ float qs[LP * AN];
-  __shared__ float mbs[LP * kThreads];
-  __shared__ float Ss[LP * kThreads];
+  __shared__ float ths[COMPAT == MF_COMPAT_GENERAL ? LP * LP : 1];
+  __shared__ float mbs[LP * RS];
+  __shared__ float Ss[LP * RS];
+  __shared__ float red[NB == 1 ? 4 * 256 : 1];
   const int L = EXACT ? LP : a.L;
   const int N = a.N, H = a.H, W = a.W;
   const int b = blockIdx.z;
@@ -43,6 +53,12 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
     float v = 0.f;
     if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = __expf(a.ell_t[base + (size_t)l * N + gy * W + gx]);
     qs[idx] = v;
+  }
+  if (COMPAT == MF_COMPAT_GENERAL) {
+    for (int f = tid; f < LP * LP; f += kThreads) {
+      const int l = f / LP, k = f - (f / LP) * LP;
+      ths[f] = (l < L && k < L) ? a.theta[l * L + k] : 0.f;
+    }
   }
   __syncthreads();
 
@@ -90,8 +106,7 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
           acc = a.potts_w * (tot - mb[k]);
         } else {
 #pragma unroll
-          for (int l = 0; l < LP; ++l)
-            if (l < L) acc = fmaf(a.theta[l * L + k], mb[l], acc);
+          for (int l = 0; l < LP; ++l) acc = fmaf(ths[l * LP + k], mb[l], acc);
         }
         a.s_bar[base + (size_t)k * N + n] = acc;
       }
@@ -99,17 +114,54 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
   }
 #pragma unroll
   for (int l = 0; l < LP; ++l) {
-    mbs[l * kThreads + tid] = mb[l];
-    Ss[l * kThreads + tid] = S[l];
+    mbs[l * RS + tid] = mb[l];
+    Ss[l * RS + tid] = S[l];
   }
   __syncthreads();
-  // Theta_bar partial of this tile: P[l][k] = sum_n mb[l][n] S[k][n]
-  const size_t part = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  for (int e = tid; e < L * L; e += kThreads) {
-    const int l = e / L, k = e - (e / L) * L;
-    float acc = 0.f;
-    for (int j = 0; j < kThreads; ++j) acc = fmaf(mbs[l * kThreads + j], Ss[k * kThreads + j], acc);
-    a.theta_part[part * L * L + e] = acc;
+  // Theta_bar partial of this tile, P[l][k] = sum_n mb[l][n] S[k][n]: an
+  // (L x 256) (256 x L) product on v_mfma_f32_16x16x4f32 with L padded to
+  // 16 NB.  Lane x of a wavefront reads A[x % 16][x / 16] = mb[row][node]
+  // and B[x / 16][x % 16] = S[col][node] and holds rows 4 (x / 16) + i,
+  // column x % 16 of the output block.  With NB = 2 each of the four
+  // wavefronts owns one 16 x 16 output block; with NB = 1 they split the
+  // 256 nodes and their sums are added in a fixed order.
+  {
+    constexpr int NOB = NB * NB, WPB = 4 / NOB, KJ = kThreads / WPB;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ob = wave / WPB, kpart = wave - ob * WPB;
+    const int rb = ob / NB, cb = ob - rb * NB;
+    const int la = 16 * rb + (lane & 15), kc = 16 * cb + (lane & 15);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int j0 = kpart * KJ + (lane >> 4);
+#pragma unroll 8
+    for (int kb = 0; kb < KJ / 4; ++kb) {
+      const int j = j0 + 4 * kb;
+      const float av = la < LP ? mbs[la * RS + j] : 0.f;
+      const float bv = kc < LP ? Ss[kc * RS + j] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    }
+    const size_t part = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float* out = a.theta_part + part * L * L;
+    if constexpr (WPB == 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int l = 16 * rb + 4 * (lane >> 4) + i;
+        if (l < L && kc < L) out[l * L + kc] = acc[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[wave * 256 + lane * 4 + i] = acc[i];
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float v = ((red[lane * 4 + i] + red[256 + lane * 4 + i]) + red[512 + lane * 4 + i]) +
+                          red[768 + lane * 4 + i];
+          const int l = 4 * (lane >> 4) + i;
+          if (l < L && kc < L) out[l * L + kc] = v;
+        }
+      }
+    }
   }
 }
 
@@ -159,13 +211,33 @@ __global__ __launch_bounds__(kThreads) void adj_b_kernel(AdjointArgs a) {
   }
 }
 
-// theta_acc[e] += sum over parts of theta_part[part][e], fixed order, FP64.
-__global__ __launch_bounds__(256) void adj_theta_reduce(const float* __restrict__ part, int n_parts, int LL,
+// theta_acc[e] += sum over tiles of theta_part[tile][e] in FP64, in a fixed
+// order: stage 1, block c sums tiles [32 c, 32 c + 32) (loads coalesced over
+// e); stage 2 adds the stage-1 sums in block order.
+__global__ __launch_bounds__(256) void adj_theta_stage(const float* __restrict__ part, int n_parts, int LL,
+                                                       double* __restrict__ stage) {
+  const int c = blockIdx.x;
+  const int k0 = c * kThetaChunk;
+  const int k1 = k0 + kThetaChunk < n_parts ? k0 + kThetaChunk : n_parts;
+  for (int e = threadIdx.x; e < LL; e += 256) {
+    // fixed order; the loads of the chunk are issued before the adds
+    float v[kThetaChunk];
+#pragma unroll
+    for (int k = 0; k < kThetaChunk; ++k) v[k] = k0 + k < k1 ? part[(size_t)(k0 + k) * LL + e] : 0.f;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kThetaChunk; ++k) s += (double)v[k];
+    stage[(size_t)c * LL + e] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void adj_theta_finish(const double* __restrict__ stage, int n_stage, int LL,
                                                         double* __restrict__ acc) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= LL) return;
   double s = 0.0;
-  for (int k = 0; k < n_parts; ++k) s += (double)part[(size_t)k * LL + e];
+#pragma unroll 16
+  for (int c = 0; c < n_stage; ++c) s += stage[(size_t)c * LL + e];
   acc[e] += s;
 }
 
@@ -218,7 +290,12 @@ hipError_t adj_lp(const AdjointArgs& a, int conn, int compat, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int n_parts = (int)(grid.x * grid.y * grid.z);
   const int LL = a.L * a.L;
-  hipLaunchKernelGGL(adj_theta_reduce, dim3((LL + 255) / 256), dim3(256), 0, s, a.theta_part, n_parts, LL, a.theta_acc);
+  const int n_stage = (n_parts + kThetaChunk - 1) / kThetaChunk;
+  hipLaunchKernelGGL(adj_theta_stage, dim3(n_stage), dim3(256), 0, s, a.theta_part, n_parts, LL, a.theta_stage);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_theta_finish, dim3((LL + 255) / 256), dim3(256), 0, s, a.theta_stage, n_stage, LL,
+                     a.theta_acc);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (conn == 4) hipLaunchKernelGGL((adj_b_kernel<LP, EXACT, 4>), grid, dim3(kThreads), 0, s, a);
@@ -230,6 +307,10 @@ hipError_t adj_lp(const AdjointArgs& a, int conn, int compat, hipStream_t s) {
 
 size_t adjoint_theta_parts(int B, int H, int W) {
   return (size_t)B * ((H + kTileY - 1) / kTileY) * ((W + kTileX - 1) / kTileX);
+}
+
+size_t adjoint_theta_stages(int B, int H, int W) {
+  return (adjoint_theta_parts(B, H, W) + kThetaChunk - 1) / kThetaChunk;
 }
 
 hipError_t launch_adjoint_step(const AdjointArgs& a, int conn, int compat, hipStream_t s) {

@@ -18,12 +18,14 @@
 // Work split: a workgroup owns a 64-row block and one of KS slices of the
 // j range; each of its four wavefronts accumulates a 16 x 32 (rows x
 // labels, L padded to 32) tile in registers.  Slices write FP32 partial
-// sums; the last workgroup of a row block to finish (counted with a
-// device-scope atomic, after a release fence) adds the KS partials in a
-// fixed order and runs the per-node step, so the result is deterministic.
-// That workgroup also writes the next Q planes and the block's column sums
-// of q, which the co-occurrence term of the next step reduces in a fixed
-// order.
+// sums.  A second kernel, one wavefront per 64-row block, adds the KS
+// partials in a fixed order and runs the per-node step, so the result is
+// deterministic; it also writes the next Q planes and the block's column
+// sums of q, which the co-occurrence term of the next step reduces in a
+// fixed order.  The hand-off between the two is the kernel boundary: the
+// eight XCDs of the MI355X have separate L2 caches, and a device-scope
+// fence per workgroup (to hand the partials to a last-arriving workgroup
+// inside one kernel) writes back the issuing XCD's L2 every time.
 #include <hip/hip_runtime.h>
 
 #include "mf_internal.h"
@@ -92,144 +94,269 @@ __global__ __launch_bounds__(64) void dense_prepare_kernel(DenseStepArgs a) {
     const float t = wave_sum_f(q);
     if (lane == 0) a.t_out[((size_t)b * a.NRB + rb) * kLP + l] = t;
   }
-  if (lane == 0) a.counters[b * a.NRB + rb] = 0;
 }
 
-template <int NS, int COMPAT, bool COOC>
-__global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a, float one_minus_alpha) {
+// One workgroup: the 64-row block rb against the j slice ks.  Each of the
+// four wavefronts holds the whole 64 x 32 tile (four 16-row MFMA tiles) and
+// takes every fourth 32-column step of the slice, so a Q operand it loads
+// meets four K operands and no two wavefronts load the same Q columns.  The
+// four per-wavefront tiles are added through LDS in wavefront order.
+//
+// ALIGNED (N a multiple of 8): K rows are read with unchecked 16-byte
+// loads.  Rows at or past N are clamped to N - 1 (their S rows are never
+// read) and columns at or past N to N - 8 (they meet Q columns, which are
+// zero past N), so the loop has no branch.
+constexpr int kPSt = kLP + 1;    // LDS row stride of the per-wavefront tiles
+
+template <int NS, bool ALIGNED>
+__global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
+  __shared__ float part[4 * kRB * kPSt];
   const int b = blockIdx.y;
   const int rb = blockIdx.x / a.KS, ks = blockIdx.x - (blockIdx.x / a.KS) * a.KS;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int L = a.L, N = a.N, Np = a.Np;
+  const int N = a.N, Np = a.Np;
   const unsigned short* __restrict__ K = a.K;
   const unsigned short* __restrict__ Q = a.q_in + (size_t)b * NS * kLP * Np;
 
-  // --- S partial = K[rows, j-slice] Q[j-slice, :] on MFMA -------------------
-  const int r0 = rb * kRB + wave * 16;
-  const int row = r0 + (lane & 15);
   const int kq = 8 * (lane >> 4);
   const int jb = ks * a.jchunk;
-  const int je = min(jb + a.jchunk, Np);
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  const bool vec_ok = (N & 7) == 0;
-  for (int j0 = jb; j0 < je; j0 += 32) {
-    const int kk = j0 + kq;
+  const int nst = (min(jb + a.jchunk, Np) - jb) / 32;   // Np and jchunk are multiples of 32
+  int row[4];
+  const unsigned short* krow[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    row[t] = rb * kRB + 16 * t + (lane & 15);
+    krow[t] = K + (size_t)(row[t] < N ? row[t] : N - 1) * N;
+  }
+  auto load_k = [&](int t, int kk) {
     bf16x8 av;
-    if (vec_ok && row < N && kk + 8 <= N) {
-      av = *reinterpret_cast<const bf16x8*>(K + (size_t)row * N + kk);
+    if constexpr (ALIGNED) {
+      av = *reinterpret_cast<const bf16x8*>(krow[t] + (kk < N ? kk : N - 8));
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const unsigned short v = (row < N && kk + e < N) ? K[(size_t)row * N + kk + e] : (unsigned short)0;
+        const unsigned short v = (row[t] < N && kk + e < N) ? krow[t][kk + e] : (unsigned short)0;
         av[e] = __builtin_bit_cast(__bf16, v);
       }
     }
+    return av;
+  };
+  const unsigned short* qlane = Q + (size_t)(lane & 15) * Np + kq;
+  auto load_q = [&](int j0, int p, int half) {
+    return *reinterpret_cast<const bf16x8*>(qlane + (size_t)(p * kLP + 16 * half) * Np + j0);
+  };
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t][0] = acc[t][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // two of the wavefront's steps per trip: all their loads before their MFMAs
+  constexpr int U = 2;
+  int st = wave;
+  for (; st + 4 * (U - 1) < nst; st += 4 * U) {
+    bf16x8 av[U][4], bq[U][NS][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j0 = jb + 32 * (st + 4 * u);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[u][t] = load_k(t, j0 + kq);
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        bq[u][p][0] = load_q(j0, p, 0);
+        bq[u][p][1] = load_q(j0, p, 1);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int p = 0; p < NS; ++p)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u][t], bq[u][p][0], acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u][t], bq[u][p][1], acc[t][1], 0, 0, 0);
+        }
+  }
+  for (; st < nst; st += 4) {
+    const int j0 = jb + 32 * st;
+    bf16x8 av[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) av[t] = load_k(t, j0 + kq);
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
-      const unsigned short* qp = Q + ((size_t)p * kLP + (lane & 15)) * Np + kk;
-      const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(qp);
-      const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(qp + (size_t)16 * Np);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc1, 0, 0, 0);
-    }
-  }
-  // lane holds rows r0 + 4*(lane/16) + i, labels lane%16 and 16 + lane%16
-  float* sp = a.s_part + ((size_t)b * a.KS + ks) * Np * kLP;
+      const bf16x8 b0 = load_q(j0, p, 0), b1 = load_q(j0, p, 1);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = r0 + 4 * (lane >> 4) + i;
-    sp[(size_t)r * kLP + (lane & 15)] = acc0[i];
-    sp[(size_t)r * kLP + 16 + (lane & 15)] = acc1[i];
-  }
-
-  // --- the last slice of this row block runs the per-node step ---------------
-  __shared__ int is_last;
-  __shared__ float Ts[kLP];
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) is_last = (atomicAdd(&a.counters[b * a.NRB + rb], 1) == a.KS - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  if (COOC) {
-    if (tid < kLP) {
-      float t = 0.f;
-      for (int k = 0; k < a.NRB; ++k) t += a.t_in[((size_t)b * a.NRB + k) * kLP + tid];
-      Ts[tid] = t;
+      for (int t = 0; t < 4; ++t) {
+        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], b0, acc[t][0], 0, 0, 0);
+        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], b1, acc[t][1], 0, 0, 0);
+      }
     }
-    __syncthreads();
   }
-  if (tid == 0) a.counters[b * a.NRB + rb] = 0;
-  if (wave != 0) return;
+  // lane holds rows 16 t + 4 (lane / 16) + i, labels lane % 16 and 16 + lane % 16
+  float* pw = part + wave * kRB * kPSt;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * t + 4 * (lane >> 4) + i;
+      pw[r * kPSt + (lane & 15)] = acc[t][0][i];
+      pw[r * kPSt + 16 + (lane & 15)] = acc[t][1][i];
+    }
+  __syncthreads();
+  float* sp = a.s_part + (((size_t)b * a.KS + ks) * Np + (size_t)rb * kRB) * kLP;
+#pragma unroll
+  for (int r = 0; r < kRB * kLP / 256; ++r) {
+    const int f = tid + 256 * r, o = (f / kLP) * kPSt + (f % kLP);
+    sp[f] = ((part[o] + part[kRB * kPSt + o]) + part[2 * kRB * kPSt + o]) + part[3 * kRB * kPSt + o];
+  }
+}
+
+// The per-node step of one 64-row block: the KS partial sums of S in a fixed
+// order, the message, the step, the next Q planes and the block's column
+// sums of q.  256 threads: lane = node of the block, wavefront w = label
+// group (labels w + 4 j, j < 8).  The partials arrive node-major and are
+// transposed through LDS (coalesced loads); the terms that mix labels
+// (Theta S, the co-occurrence product, the per-node max and sum) read the
+// node's other labels from LDS.  LC > 0 fixes L at compile time so the
+// label loops unroll; every global load is issued before the first wait.
+constexpr int kEpiThreads = 256;
+constexpr int kSt = kLP + 1;          // LDS row stride of the node x label tiles
+constexpr int kTParts = kEpiThreads / kLP;
+
+template <int NS, int COMPAT, bool COOC, int LC>
+__global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepArgs a, float one_minus_alpha) {
+  const int rb = blockIdx.x, b = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int L = LC > 0 ? LC : a.L, N = a.N, Np = a.Np;
+  __shared__ float St[kRB * kSt];      // S[node][label]
+  __shared__ float Qt[kRB * kSt];      // q[node][label] (co-occurrence)
+  __shared__ float red[4 * kRB];       // per-node partials of the four label groups
+  __shared__ float Tp[kEpiThreads];    // partial column sums of q at the previous step
+  __shared__ float Ts[kLP];
 
   const int i = rb * kRB + lane;
   const bool inside = i < N;
-  float S[kLP], ell[kLP], z[kLP], e[kLP];
+  const size_t base = (size_t)b * L * N + (inside ? i : 0);
+  constexpr int J = kLP / 4;
+  float ell[J], un[J], z[J];
 #pragma unroll
-  for (int l = 0; l < kLP; ++l) S[l] = 0.f;
-  for (int k = 0; k < a.KS; ++k) {
-    const float4* src = reinterpret_cast<const float4*>(a.s_part + (((size_t)b * a.KS + k) * Np + i) * kLP);
+  for (int j = 0; j < J; ++j) {
+    const int l = w + 4 * j;
+    const bool on = inside && l < L;
+    ell[j] = on ? a.state_in[base + (size_t)l * N] : 0.f;
+    un[j] = on ? a.unary[base + (size_t)l * N] : 0.f;
+  }
+  if (COOC) {
+    // column sums: label tid % 32, blocks tid / 32 + 8 k in order
+    const int l = tid % kLP;
+    float t = 0.f;
+#pragma unroll 8
+    for (int k = tid / kLP; k < a.NRB; k += kTParts) t += a.t_in[((size_t)b * a.NRB + k) * kLP + l];
+    Tp[tid] = t;
+  }
+  // S = sum over the KS slices, element by element in slice order
+  {
+    const float* sp = a.s_part + ((size_t)b * a.KS * Np + (size_t)rb * kRB) * kLP;
+    float acc[kRB * kLP / kEpiThreads];
 #pragma unroll
-    for (int v = 0; v < kLP / 4; ++v) {
-      const float4 x = src[v];
-      S[4 * v] += x.x;
-      S[4 * v + 1] += x.y;
-      S[4 * v + 2] += x.z;
-      S[4 * v + 3] += x.w;
+    for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) acc[r] = 0.f;
+#pragma unroll 4
+    for (int k = 0; k < a.KS; ++k) {
+#pragma unroll
+      for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) acc[r] += sp[(size_t)k * Np * kLP + tid + r * kEpiThreads];
+    }
+#pragma unroll
+    for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) {
+      const int f = tid + r * kEpiThreads;
+      St[(f / kLP) * kSt + (f % kLP)] = acc[r];
     }
   }
-  const size_t base = (size_t)b * L * N + (inside ? i : 0);
-  float qo[kLP];
+  if (COOC) {
 #pragma unroll
-  for (int l = 0; l < kLP; ++l) {
-    ell[l] = (inside && l < L) ? a.state_in[base + (size_t)l * N] : 0.f;
-    qo[l] = (inside && l < L) ? __expf(ell[l]) : 0.f;
+    for (int j = 0; j < J; ++j) Qt[lane * kSt + w + 4 * j] = (inside && w + 4 * j < L) ? __expf(ell[j]) : 0.f;
+  }
+  __syncthreads();
+  if (COOC && tid < kLP) {
+    float t = 0.f;
+#pragma unroll
+    for (int p = 0; p < kTParts; ++p) t += Tp[p * kLP + tid];
+    Ts[tid] = t;
   }
 
   float tot = 0.f;
   if (COMPAT == MF_COMPAT_POTTS) {
+    float part = 0.f;
 #pragma unroll
-    for (int l = 0; l < kLP; ++l) tot += (l < L) ? S[l] : 0.f;
+    for (int j = 0; j < J; ++j) part += (w + 4 * j < L) ? St[lane * kSt + w + 4 * j] : 0.f;
+    red[w * kRB + lane] = part;
+  }
+  __syncthreads();
+  if (COMPAT == MF_COMPAT_POTTS) tot = (red[lane] + red[kRB + lane]) + (red[2 * kRB + lane] + red[3 * kRB + lane]);
+  // the node's S and q rows, read once
+  float srow[kLP], qrow[kLP];
+  if (COMPAT != MF_COMPAT_POTTS) {
+#pragma unroll
+    for (int k = 0; k < kLP; ++k) srow[k] = (LC == 0 || k < L) ? St[lane * kSt + k] : 0.f;
+  }
+  if (COOC) {
+#pragma unroll
+    for (int k = 0; k < kLP; ++k) qrow[k] = (LC == 0 || k < L) ? Ts[k] - Qt[lane * kSt + k] : 0.f;
   }
   float mx = -INFINITY;
 #pragma unroll
-  for (int l = 0; l < kLP; ++l) {
-    z[l] = -INFINITY;
+  for (int j = 0; j < J; ++j) {
+    const int l = w + 4 * j;
+    z[j] = -INFINITY;
     if (l < L) {
-      float m = inside ? a.unary[base + (size_t)l * N] : 0.f;
+      float m = un[j];
       if (COMPAT == MF_COMPAT_POTTS) {
-        m += a.potts_w * (tot - S[l]);
+        m += a.potts_w * (tot - St[lane * kSt + l]);
       } else {
         float acc = 0.f;
+        if constexpr (LC > 0) {
 #pragma unroll
-        for (int k = 0; k < kLP; ++k)
-          if (k < L) acc = fmaf(a.theta[l * L + k], S[k], acc);
+          for (int k = 0; k < LC; ++k) acc = fmaf(a.theta[l * LC + k], srow[k], acc);
+        } else {
+          for (int k = 0; k < L; ++k) acc = fmaf(a.theta[l * L + k], St[lane * kSt + k], acc);
+        }
         m += acc;
       }
       if (COOC) {
         float c = 0.f;
+        if constexpr (LC > 0) {
 #pragma unroll
-        for (int k = 0; k < kLP; ++k)
-          if (k < L) c = fmaf(a.cooc[l * L + k], Ts[k] - qo[k], c);
+          for (int k = 0; k < LC; ++k) c = fmaf(a.cooc[l * LC + k], qrow[k], c);
+        } else {
+          for (int k = 0; k < L; ++k) c = fmaf(a.cooc[l * L + k], Ts[k] - Qt[lane * kSt + k], c);
+        }
         m += c * a.inv_n;
       }
-      z[l] = one_minus_alpha * ell[l] - a.alpha * m;
-      mx = fmaxf(mx, z[l]);
+      z[j] = one_minus_alpha * ell[j] - a.alpha * m;
+      mx = fmaxf(mx, z[j]);
     }
   }
+  // per-node max and sum over the four label groups, fixed order
+  __syncthreads();
+  red[w * kRB + lane] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[lane], red[kRB + lane]), fmaxf(red[2 * kRB + lane], red[3 * kRB + lane]));
+  __syncthreads();
+  float e[J];
   float se = 0.f;
 #pragma unroll
-  for (int l = 0; l < kLP; ++l) {
-    e[l] = (l < L) ? __expf(z[l] - mx) : 0.f;
-    se += e[l];
+  for (int j = 0; j < J; ++j) {
+    e[j] = (w + 4 * j < L) ? __expf(z[j] - mx) : 0.f;
+    se += e[j];
   }
+  red[w * kRB + lane] = se;
+  __syncthreads();
+  se = (red[lane] + red[kRB + lane]) + (red[2 * kRB + lane] + red[3 * kRB + lane]);
   const float lse = mx + __logf(se);
   const float inv = 1.0f / se;
   unsigned short* planes = a.q_out + (size_t)b * NS * kLP * Np;
 #pragma unroll
-  for (int l = 0; l < kLP; ++l) {
-    const float q = inside ? e[l] * inv : 0.f;
-    if (inside && l < L) a.state_out[base + (size_t)l * N] = z[l] - lse;
+  for (int j = 0; j < J; ++j) {
+    const int l = w + 4 * j;
+    const float q = inside ? e[j] * inv : 0.f;
+    if (inside && l < L) a.state_out[base + (size_t)l * N] = z[j] - lse;
     store_planes<NS>(planes, Np, l, i, q);
     const float t = wave_sum_f(q);
     if (lane == 0) a.t_out[((size_t)b * a.NRB + rb) * kLP + l] = t;
@@ -312,20 +439,32 @@ __global__ __launch_bounds__(256) void dense_fe_kernel(DenseFreeEnergyArgs a) {
   if (threadIdx.x == 0) a.partials[(size_t)b * a.n_blocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-template <int NS>
-hipError_t step_ns(const DenseStepArgs& a, int compat, hipStream_t s) {
-  dim3 grid(a.NRB * a.KS, a.B);
-  const float om = (float)(1.0 - (double)a.alpha);
+template <int NS, int LC>
+hipError_t epilogue_lc(const DenseStepArgs& a, int compat, float om, hipStream_t s) {
+  const dim3 grid(a.NRB, a.B);
   const bool cooc = a.cooc != nullptr;
   if (compat == MF_COMPAT_POTTS) {
-    if (cooc) hipLaunchKernelGGL((dense_step_kernel<NS, MF_COMPAT_POTTS, true>), grid, dim3(256), 0, s, a, om);
-    else hipLaunchKernelGGL((dense_step_kernel<NS, MF_COMPAT_POTTS, false>), grid, dim3(256), 0, s, a, om);
+    if (cooc) hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_POTTS, true, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
+    else hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_POTTS, false, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
   } else {
-    if (cooc) hipLaunchKernelGGL((dense_step_kernel<NS, MF_COMPAT_GENERAL, true>), grid, dim3(256), 0, s, a, om);
-    else hipLaunchKernelGGL((dense_step_kernel<NS, MF_COMPAT_GENERAL, false>), grid, dim3(256), 0, s, a, om);
+    if (cooc) hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_GENERAL, true, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
+    else hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_GENERAL, false, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
   }
   return hipGetLastError();
 }
+
+template <int NS>
+hipError_t step_ns(const DenseStepArgs& a, int compat, hipStream_t s) {
+  if (a.N % 8 == 0)
+    hipLaunchKernelGGL((dense_step_kernel<NS, true>), dim3(a.NRB * a.KS, a.B), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((dense_step_kernel<NS, false>), dim3(a.NRB * a.KS, a.B), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const float om = (float)(1.0 - (double)a.alpha);
+  return a.L == 21 ? epilogue_lc<NS, 21>(a, compat, om, s) : epilogue_lc<NS, 0>(a, compat, om, s);
+}
+
 
 }  // namespace
 

@@ -64,8 +64,6 @@ mf::WorkspaceLayout layout_for(const mf_desc& d) {
     off += align256(sizeof(float) * B * (size_t)w.dg.KS * Np * 32);
     w.dt = off;
     off += align256(sizeof(float) * 2 * B * (size_t)w.dg.NRB * 32);
-    w.dc = off;
-    off += align256(sizeof(int) * B * (size_t)w.dg.NRB);
     w.dqd = off;
     off += align256(sizeof(double) * B * (size_t)d.n_nodes * (size_t)d.n_labels);
   }
@@ -186,7 +184,6 @@ mf::DenseStepArgs dense_args(const mf_handle* h, int from) {
   a.s_part = (float*)ws_at(h, w.ds);
   a.t_in = (const float*)ws_at(h, w.dt) + (size_t)from * t_elems;
   a.t_out = (float*)ws_at(h, w.dt) + (size_t)(from ^ 1) * t_elems;
-  a.counters = (int*)ws_at(h, w.dc);
   a.theta = d.theta;
   a.cooc = d.cooc;
   a.B = d.batch;
@@ -624,6 +621,7 @@ size_t mf_backward_workspace_size(const mf_handle* h, int32_t ckpt_every) {
   off += align256(sizeof(float) * E);                              // Theta^T m_bar
   off += align256(sizeof(float) * LL * mf::adjoint_theta_parts(d.batch, d.height, d.width));
   off += align256(sizeof(double) * LL);
+  off += align256(sizeof(double) * LL * mf::adjoint_theta_stages(d.batch, d.height, d.width));
   return off;
 }
 
@@ -654,6 +652,8 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
   float* part = (float*)w;
   w += align256(sizeof(float) * LL * mf::adjoint_theta_parts(d.batch, d.height, d.width));
   double* acc = (double*)w;
+  w += align256(sizeof(double) * LL);
+  double* stage = (double*)w;
   const hipStream_t s = h->stream;
   const int conn = d.graph == MF_GRID4 ? 4 : 8;
   auto dev_fail = [&](hipError_t e, const char* what) {
@@ -696,6 +696,7 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
       a.s_bar = Sb;
       a.theta = d.theta;
       a.theta_part = part;
+      a.theta_stage = stage;
       a.theta_acc = acc;
       a.B = d.batch;
       a.L = d.n_labels;

@@ -85,7 +85,6 @@ struct DenseStepArgs {
   float* s_part;           // [B][KS][Np][32] partial S
   const float* t_in;       // [B][NRB][32] column sums of q(state_in) per row block
   float* t_out;
-  int* counters;           // [B][NRB] slice arrival counters (zero between launches)
   const float* theta;      // [L][L] (general)
   const float* cooc;       // [L][L] or nullptr
   int B, L, N, Np, KS, NRB, jchunk;
@@ -147,6 +146,7 @@ struct AdjointArgs {
   float* s_bar;            // [B][L][N] scratch: Theta^T m_bar
   const float* theta;
   float* theta_part;       // [parts][L][L]
+  double* theta_stage;     // [stages][L][L] FP64 sums of 32 tile partials each
   double* theta_acc;       // [L][L] accumulated
   int B, L, N, H, W;
   float alpha, potts_w;
@@ -161,7 +161,6 @@ struct WorkspaceLayout {
   size_t dq = 0;           // uint16[2][B][NS][32][Np] q planes (dense only)
   size_t ds = 0;           // float[B][KS][Np][32] partial S
   size_t dt = 0;           // float[2][B][NRB][32] column sums
-  size_t dc = 0;           // int[B][NRB] counters
   size_t dqd = 0;          // double[B][N][L] free-energy scratch
   size_t rule_state = 0;   // float[1 or 2][B][L][N] momentum / ADAM state
   DenseGeometry dg;
@@ -205,6 +204,7 @@ hipError_t launch_csr_step(const CsrStepArgs& a, int compat, hipStream_t s);
 hipError_t launch_csr_free_energy(const CsrFreeEnergyArgs& a, int compat, hipStream_t s);
 
 size_t adjoint_theta_parts(int B, int H, int W);
+size_t adjoint_theta_stages(int B, int H, int W);
 hipError_t launch_adjoint_step(const AdjointArgs& a, int conn, int compat, hipStream_t s);
 hipError_t launch_adjoint_init(const float* g0, const float* ell0, float* u_bar, int B, int L, int N,
                                hipStream_t s);

@@ -101,7 +101,7 @@ def test_dense_small_end_to_end_and_free_energy(small):
 
 
 @pytest.mark.parametrize("n,L,cooc,potts", [(64, 2, False, True), (129, 21, True, True), (517, 7, False, False),
-                                            (1000, 32, True, False)])
+                                            (1000, 32, True, False), (300, 21, True, False), (776, 21, False, False)])
 def test_dense_variants(n, L, cooc, potts):
     base = synth.dense_instance(5 + n, n, L, pos_high=16.0, iters=6, with_cooc=cooc)
     if not potts:
