@@ -46,7 +46,13 @@ WORKLOADS = {
     "grid2048_L21_theta": lambda s: s.workload_big(),
     "grid32_L2_potts": lambda s: s.workload_c1(),
     "batch16_grid128_L21": lambda s: s.workload_c5(),
+    # one step = the forward solve with checkpoints and the adjoint back to u and Theta
+    "batch16_grid128_L21_adjoint": lambda s: s.workload_c5(),
+    "dense4096_L21_cooc": lambda s: s.workload_c3(),
+    "csr65536_L21": lambda s: s.csr_instance(8, 65536, 21, avg_degree=8, weighted=True, alpha=0.5, iters=100,
+                                             name="csr65536_L21"),
 }
+ADJOINT_CKPT = 5
 
 
 def log(*a):
@@ -61,16 +67,34 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def make_solver(inst, torch, mf):
+def make_solver(inst, torch, mf, **extra):
     dev = torch.device("cuda:0")
     u = torch.from_numpy(inst.unary).to(dev)
-    kw = dict(alpha=inst.alpha)
+    kw = dict(alpha=inst.alpha, **extra)
     if inst.theta is not None:
         kw["theta"] = torch.from_numpy(inst.theta).to(dev)
     else:
         kw["potts_w"] = inst.potts_w
-    graph = "grid4" if inst.graph == 0 else "grid8"
-    return mf.MeanField(u, graph, height=inst.height, width=inst.width, **kw)
+    if inst.graph in (0, 1):
+        graph = "grid4" if inst.graph == 0 else "grid8"
+        return mf.MeanField(u, graph, height=inst.height, width=inst.width, **kw)
+    if inst.graph == 2:
+        return mf.MeanField(u, "csr", csr_row_ptr=torch.from_numpy(inst.row_ptr).to(dev),
+                            csr_col=torch.from_numpy(inst.col).to(dev),
+                            csr_w=None if inst.csr_w is None else torch.from_numpy(inst.csr_w).to(dev), **kw)
+    K = mf.dense_kernel(torch.from_numpy(inst.features).to(dev))
+    cooc = None if inst.cooc is None else torch.from_numpy(inst.cooc).to(dev)
+    return mf.MeanField(u, "dense", dense_K=K, cooc=cooc, **kw)
+
+
+def algorithmic_bytes(inst, k):
+    """Unique bytes one launch of the dominant kernel must move, k steps."""
+    B, L, N = inst.unary.shape
+    if inst.graph == 3:      # dense: the BF16 K stream (2 N^2 B) and the state (12 B per node-label)
+        return k * B * (2 * N * N + BYTES_PER_UPDATE * N * L)
+    if inst.graph == 2:      # CSR: log q, u, log q' and the node-major q copy written and gathered
+        return k * B * N * L * (BYTES_PER_UPDATE + 8)
+    return BYTES_PER_UPDATE * B * N * L * k
 
 
 def time_step_launches(solver, torch, launches):
@@ -98,11 +122,83 @@ def step_kernel_name(inst, k):
     dispatch rule: fused steps for k > 1, Theta S on the matrix cores for a
     general Theta with 8 < L <= 32)."""
     L = inst.unary.shape[1]
+    if inst.graph == 3:
+        return "mf::dense_step_kernel"
+    if inst.graph == 2:
+        return "mf::csr_step_kernel"
     if k == 1:
         return "mf::lanes::step_kernel"
     if inst.theta is not None and 8 < L <= 32:
         return "mf::temporal::multi_step_mfma_kernel"
     return "mf::temporal::multi_step_kernel"
+
+
+METRIC = "node-label updates/s (N*L*iters/s) at oracle-matched marginals"
+GRAPH_NAMES = {0: "grid4", 1: "grid8", 2: "csr", 3: "dense"}
+
+
+def workload_config(inst, step):
+    B, L, N = inst.unary.shape
+    cfg = {"workload": inst.name, "graph": GRAPH_NAMES[inst.graph], "nodes": N, "labels": L, "batch": B,
+           "compat": "theta" if inst.theta is not None else "potts", "alpha": inst.alpha, "iters": inst.iters,
+           "step": step}
+    if inst.graph in (0, 1):
+        cfg.update(height=inst.height, width=inst.width, connectivity=4 if inst.graph == 0 else 8)
+    if inst.graph == 2:
+        cfg["edges"] = int(inst.col.size)
+    if inst.graph == 3:
+        cfg["cooc"] = inst.cooc is not None
+    return cfg
+
+
+def bench_adjoint(args, inst, torch, mf):
+    """One step = the forward solve of T steps (one per launch, checkpoints every
+    ADJOINT_CKPT) and the hand-written adjoint back to the unaries and Theta,
+    through torch.autograd on the library (paper_1511_06103_amd.autograd)."""
+    from paper_1511_06103_amd import autograd, synth
+    B, L, N = inst.unary.shape
+    T = inst.iters
+    dev = torch.device("cuda:0")
+    u = torch.from_numpy(inst.unary).to(dev).requires_grad_(True)
+    th = torch.from_numpy(inst.theta).to(dev).requires_grad_(True)
+    c = torch.from_numpy(synth.adjoint_loss_weights(55, inst.unary.shape)).to(dev)
+
+    def step():
+        u.grad = None
+        th.grad = None
+        ell = autograd.unrolled_mean_field(u, th, height=inst.height, width=inst.width, connectivity=8,
+                                           alpha=inst.alpha, iters=T, ckpt_every=ADJOINT_CKPT)
+        (torch.exp(ell) * c).sum().backward()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        lat.append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in lat])
+    value = B * N * L * T * args.steps / wall
+    # forward 12 B, recompute 12 B and adjoint about 24 B per node-label-step
+    algo = 48 * B * N * L * T
+    per = wall / args.steps
+    out = {"metric": METRIC, "value": value, "unit": "node-label updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": per * 1e3, "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": workload_config(inst, "forward solve with checkpoints + adjoint to u and Theta"),
+           "roofline": {"bound": "hbm", "achieved": round(algo / per / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(algo / per / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "forward + backward (all kernels of one training step)",
+                        "algorithmic_bytes_per_step": algo},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(inst, budget_s=12.0):
@@ -111,10 +207,17 @@ def cpu_baseline(inst, budget_s=12.0):
 
     import oracle as O
     b = 0
-    conn = 4 if inst.graph == 0 else 8
     th = None if inst.theta is None else inst.theta.astype(np.float64)
     pw = None if inst.theta is not None else inst.potts_w
-    model = O.grid_model(inst.unary[b].astype(np.float64), inst.height, inst.width, conn, theta=th, potts_w=pw)
+    u = inst.unary[b].astype(np.float64)
+    if inst.graph in (0, 1):
+        model = O.grid_model(u, inst.height, inst.width, 4 if inst.graph == 0 else 8, theta=th, potts_w=pw)
+    elif inst.graph == 2:
+        model = O.csr_model(u, inst.row_ptr, inst.col, inst.csr_w, theta=th, potts_w=pw)
+    else:
+        K = O.round_to_bf16(O.gaussian_kernel(inst.features))
+        cooc = None if inst.cooc is None else inst.cooc.astype(np.float64)
+        model = O.dense_model(u, K, theta=th, potts_w=pw, cooc=cooc)
     with threadpool_limits(1):
         ell = O.init_state(model.unary)
         O.prox_step(ell, model, inst.alpha)     # build caches outside the timing
@@ -126,7 +229,7 @@ def cpu_baseline(inst, budget_s=12.0):
         el = time.perf_counter() - t0
     L, N = model.unary.shape
     return {"value": steps * N * L / el, "unit": "node-label updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 proximal steps of one {inst.height}x{inst.width} L={L} problem "
+            "sample": f"{steps} FP64 proximal steps of one {inst.name} problem (N={N}, L={L}) "
                       f"({el:.1f} s, 1 thread)"}
 
 
@@ -183,6 +286,8 @@ def main():
     B, L, N = inst.unary.shape
     T = inst.iters
     log(f"workload {inst.name}: B={B} N={N} L={L} T={T} alpha={inst.alpha}")
+    if args.workload.endswith("_adjoint"):
+        return bench_adjoint(args, inst, torch, mf)
     solver = make_solver(inst, torch, mf)
     q = torch.empty_like(solver.unary)
 
@@ -218,7 +323,7 @@ def main():
 
     # dominant kernel: one step-kernel launch = K steps over all B * N * L node-labels
     mean_d, k = time_step_launches(solver, torch, args.launches)
-    algo = BYTES_PER_UPDATE * B * N * L * k
+    algo = algorithmic_bytes(inst, k)
     achieved = algo / mean_d / 1e9
     traffic = load_traffic(inst.name, k)
     kname = step_kernel_name(inst, k)
@@ -235,7 +340,7 @@ def main():
         log(f"cpu oracle: {cpu['value']:.3e} updates/s ({cpu['sample']})")
 
     out = {
-        "metric": "node-label updates/s (N*L*iters/s) at oracle-matched marginals",
+        "metric": METRIC,
         "value": value,
         "unit": "node-label updates/s",
         "n_gpus": 1,
@@ -249,10 +354,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": inst.name, "height": inst.height, "width": inst.width, "labels": L,
-                   "batch": B, "connectivity": 4 if inst.graph == 0 else 8,
-                   "compat": "theta" if inst.theta is not None else "potts", "alpha": inst.alpha,
-                   "iters": T, "step": "init + iters proximal steps + write q"},
+        "config": workload_config(inst, "init + iters proximal steps + write q"),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
