@@ -146,7 +146,11 @@ typedef struct mf_desc {
   int64_t csr_nnz;
   /* Dense graph (graph == MF_DENSE): K is N x N row-major bfloat16 bits
    * (uint16), symmetric with a zero diagonal; cooc is an optional [L][L]
-   * symmetric co-occurrence energy applied to every pair with weight 1/N. */
+   * symmetric co-occurrence energy applied to every pair with weight 1/N.
+   * mf_init and mf_solve copy K into the workspace in the order the matrix
+   * cores read it; the steps read that copy, so a change to K takes effect
+   * at the next mf_init or mf_solve (mf_free_energy and mf_lipschitz read
+   * dense_K itself). */
   const uint16_t *dense_K;
   const float *cooc;
   const float *unary;      /* [B][L][N] FP32, finite */

@@ -30,6 +30,31 @@ constexpr int kThetaChunk = 32;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Stage the L label planes of a (64 + 2) x (4 + 2) halo region into LDS,
+// optionally through exp.  The trip count is fixed by LP, so every load of
+// a thread is issued before the first is used.
+template <int LP, bool EXP>
+__device__ __forceinline__ void load_halo(const float* __restrict__ src, float* __restrict__ dst, int L, int N, int H, int W,
+                                 int x0, int y0, int tid) {
+  constexpr int IT = (LP * AN + kThreads - 1) / kThreads;
+  float v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = tid + it * kThreads;
+    const int l = idx / AN;
+    const int r = idx - l * AN;
+    const int hy = r / AX, hx = r - (r / AX) * AX;
+    const int gy = y0 + hy - 1, gx = x0 + hx - 1;
+    const bool on = l < L && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    v[it] = on ? src[(size_t)l * N + gy * W + gx] : (EXP ? -INFINITY : 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = tid + it * kThreads;
+    if (idx < L * AN) dst[idx] = EXP ? __expf(v[it]) : v[it];
+  }
+}
+
 template <int LP, bool EXACT, int CONN, int COMPAT>
 __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
   constexpr int NB = (LP + 15) / 16;       // 16-label blocks of Theta_bar
@@ -45,16 +70,9 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
   const size_t base = (size_t)b * L * N;
   const int tid = threadIdx.x;
 
-  for (int idx = tid; idx < L * AN; idx += kThreads) {
-    const int l = idx / AN;
-    const int r = idx - l * AN;
-    const int hy = r / AX, hx = r - (r / AX) * AX;
-    const int gy = y0 + hy - 1, gx = x0 + hx - 1;
-    float v = 0.f;
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = __expf(a.ell_t[base + (size_t)l * N + gy * W + gx]);
-    qs[idx] = v;
-  }
+  load_halo<LP, true>(a.ell_t + base, qs, L, N, H, W, x0, y0, tid);
   if (COMPAT == MF_COMPAT_GENERAL) {
+#pragma unroll
     for (int f = tid; f < LP * LP; f += kThreads) {
       const int l = f / LP, k = f - (f / LP) * LP;
       ths[f] = (l < L && k < L) ? a.theta[l * L + k] : 0.f;
@@ -174,15 +192,7 @@ __global__ __launch_bounds__(kThreads) void adj_b_kernel(AdjointArgs a) {
   const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
   const size_t base = (size_t)b * L * N;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < L * AN; idx += kThreads) {
-    const int l = idx / AN;
-    const int r = idx - l * AN;
-    const int hy = r / AX, hx = r - (r / AX) * AX;
-    const int gy = y0 + hy - 1, gx = x0 + hx - 1;
-    float v = 0.f;
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = a.s_bar[base + (size_t)l * N + gy * W + gx];
-    sb[idx] = v;
-  }
+  load_halo<LP, false>(a.s_bar + base, sb, L, N, H, W, x0, y0, tid);
   __syncthreads();
   const int tx = tid % kTileX, ty = tid / kTileX;
   const int x = x0 + tx, y = y0 + ty;

@@ -15,17 +15,30 @@
 // (2 bytes per multiply-add pair of each row), not by the MFMA rate, so the
 // extra planes cost little.
 //
+// Layout in HBM: both MFMA operands are stored in the order the matrix
+// cores take them, so every operand load of a wavefront reads 1 KiB of
+// contiguous memory (a row-major K would make each load touch 16 rows 8 KiB
+// apart: 16 address translations and half-used cache lines per load).  K is
+// copied once per solve (mf_init, mf_solve) into the workspace as
+// [Np/64][Np/32][4][64][8]: 64-row block, 32-column chunk, 16-row tile,
+// lane, element, where lane x of tile t holds row 16 t + x % 16, columns
+// 8 (x / 16) .. + 7 of the chunk, zero past N.  The q planes are written by
+// the step itself as [Np/32][NS][2][64][8]: column chunk, plane, label half,
+// lane, element, where lane x holds label 16 h + x % 16 at nodes
+// 8 (x / 16) .. + 7 of the chunk.
+//
 // Work split: a workgroup owns a 64-row block and one of KS slices of the
-// j range; each of its four wavefronts accumulates a 16 x 32 (rows x
-// labels, L padded to 32) tile in registers.  Slices write FP32 partial
-// sums.  A second kernel, one wavefront per 64-row block, adds the KS
-// partials in a fixed order and runs the per-node step, so the result is
-// deterministic; it also writes the next Q planes and the block's column
-// sums of q, which the co-occurrence term of the next step reduces in a
-// fixed order.  The hand-off between the two is the kernel boundary: the
-// eight XCDs of the MI355X have separate L2 caches, and a device-scope
-// fence per workgroup (to hand the partials to a last-arriving workgroup
-// inside one kernel) writes back the issuing XCD's L2 every time.
+// j range; its four wavefronts split the slice's 32-column chunks and each
+// accumulates the whole 64 x 32 (rows x labels, L padded to 32) tile in
+// registers.  Slices write FP32 partial sums.  A second kernel, one
+// workgroup per 64-row block, adds the KS partials in a fixed order and
+// runs the per-node step, so the result is deterministic; it also writes
+// the next Q planes and the block's column sums of q, which the
+// co-occurrence term of the next step reduces in a fixed order.  The
+// hand-off between the two is the kernel boundary: the eight XCDs of the
+// MI355X have separate L2 caches, and a device-scope fence per workgroup
+// (to hand the partials to a last-arriving workgroup inside one kernel)
+// writes back the issuing XCD's L2 every time.
 #include <hip/hip_runtime.h>
 
 #include "mf_internal.h"
@@ -46,10 +59,23 @@ __device__ inline unsigned short f2bf_rne(float x) {
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-__device__ inline float wave_sum_f(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Sum over the 64 lanes in the VALU, one fixed order: rotations by 8, 4, 2
+// and 1 within each row of 16 lanes (DPP), then rows 0 + 1 and 2 + 3
+// (v_permlane16_swap) and the two half-waves (v_permlane32_swap).  Lane 0
+// holds the sum.
+template <int N>
+__device__ inline float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + N, 0xF, 0xF, false));
+}
+__device__ inline float wave_sum_dpp(float v) {
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
+  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // K_ij = exp(-|f_i - f_j|^2 / 2) in FP32, K_ii = 0, rounded to BF16 (nearest even).
@@ -66,16 +92,43 @@ __global__ __launch_bounds__(256) void dense_kernel_build(const float* __restric
   K[(size_t)i * n + j] = (i == j) ? (unsigned short)0 : f2bf_rne(expf(-0.5f * d2));
 }
 
-// Split q (FP32) of one node into NS BF16 planes and store them label-major.
+// Split q (FP32) of label l at node i into NS BF16 planes, stored in the
+// B-operand order of the step kernel.
 template <int NS>
-__device__ inline void store_planes(unsigned short* __restrict__ planes, int Np, int l, int i, float q) {
+__device__ inline void store_planes(unsigned short* __restrict__ planes, int l, int i, float q) {
+  const int k = i & 31;
+  const size_t at = ((size_t)(i >> 5) * NS * 2 + (l >> 4)) * 512 + ((l & 15) + 16 * (k >> 3)) * 8 + (k & 7);
   float r = q;
 #pragma unroll
   for (int p = 0; p < NS; ++p) {
     const unsigned short h = f2bf_rne(r);
-    planes[((size_t)p * kLP + l) * Np + i] = h;
+    planes[at + (size_t)p * 1024] = h;
     r -= bf2f(h);
   }
+}
+
+// K (row-major, the caller's) -> Kt (MFMA operand order, zero-padded to Np).
+// One thread per 16-byte operand slot, in Kt order: a wavefront writes 1 KiB
+// of contiguous memory and reads 64 bytes from each of 16 rows of K.
+__global__ __launch_bounds__(256) void dense_tile_k_kernel(const unsigned short* __restrict__ K, int N, int Np,
+                                                           bf16x8* __restrict__ Kt) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= (size_t)Np * (Np / 8)) return;
+  const int lane = (int)(c & 63), t = (int)((c >> 6) & 3);
+  const size_t tile = c >> 8;                       // rb * (Np / 32) + ct
+  const int ct = (int)(tile % (size_t)(Np / 32)), rb = (int)(tile / (size_t)(Np / 32));
+  const int row = 64 * rb + 16 * t + (lane & 15), col = 32 * ct + 8 * (lane >> 4);
+  bf16x8 v;
+  if ((N & 7) == 0 && row < N && col < N) {
+    v = *reinterpret_cast<const bf16x8*>(K + (size_t)row * N + col);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const unsigned short x = (row < N && col + e < N) ? K[(size_t)row * N + col + e] : (unsigned short)0;
+      v[e] = __builtin_bit_cast(__bf16, x);
+    }
+  }
+  Kt[c] = v;
 }
 
 // q^0 planes and per-block column sums from the initial state.  One
@@ -90,8 +143,8 @@ __global__ __launch_bounds__(64) void dense_prepare_kernel(DenseStepArgs a) {
   for (int l = 0; l < kLP; ++l) {
     float q = 0.f;
     if (i < N && l < L) q = __expf(a.state_in[((size_t)b * L + l) * N + i]);
-    store_planes<NS>(planes, Np, l, i, q);
-    const float t = wave_sum_f(q);
+    store_planes<NS>(planes, l, i, q);
+    const float t = wave_sum_dpp(q);
     if (lane == 0) a.t_out[((size_t)b * a.NRB + rb) * kLP + l] = t;
   }
 }
@@ -101,50 +154,22 @@ __global__ __launch_bounds__(64) void dense_prepare_kernel(DenseStepArgs a) {
 // takes every fourth 32-column step of the slice, so a Q operand it loads
 // meets four K operands and no two wavefronts load the same Q columns.  The
 // four per-wavefront tiles are added through LDS in wavefront order.
-//
-// ALIGNED (N a multiple of 8): K rows are read with unchecked 16-byte
-// loads.  Rows at or past N are clamped to N - 1 (their S rows are never
-// read) and columns at or past N to N - 8 (they meet Q columns, which are
-// zero past N), so the loop has no branch.
 constexpr int kPSt = kLP + 1;    // LDS row stride of the per-wavefront tiles
 
-template <int NS, bool ALIGNED>
+template <int NS>
 __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   __shared__ float part[4 * kRB * kPSt];
   const int b = blockIdx.y;
   const int rb = blockIdx.x / a.KS, ks = blockIdx.x - (blockIdx.x / a.KS) * a.KS;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int N = a.N, Np = a.Np;
-  const unsigned short* __restrict__ K = a.K;
-  const unsigned short* __restrict__ Q = a.q_in + (size_t)b * NS * kLP * Np;
-
-  const int kq = 8 * (lane >> 4);
-  const int jb = ks * a.jchunk;
-  const int nst = (min(jb + a.jchunk, Np) - jb) / 32;   // Np and jchunk are multiples of 32
-  int row[4];
-  const unsigned short* krow[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    row[t] = rb * kRB + 16 * t + (lane & 15);
-    krow[t] = K + (size_t)(row[t] < N ? row[t] : N - 1) * N;
-  }
-  auto load_k = [&](int t, int kk) {
-    bf16x8 av;
-    if constexpr (ALIGNED) {
-      av = *reinterpret_cast<const bf16x8*>(krow[t] + (kk < N ? kk : N - 8));
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const unsigned short v = (row[t] < N && kk + e < N) ? krow[t][kk + e] : (unsigned short)0;
-        av[e] = __builtin_bit_cast(__bf16, v);
-      }
-    }
-    return av;
-  };
-  const unsigned short* qlane = Q + (size_t)(lane & 15) * Np + kq;
-  auto load_q = [&](int j0, int p, int half) {
-    return *reinterpret_cast<const bf16x8*>(qlane + (size_t)(p * kLP + 16 * half) * Np + j0);
-  };
+  const int Np = a.Np;
+  const int c0 = ks * (a.jchunk / 32);                           // first 32-column chunk of the slice
+  const int nst = (min((ks + 1) * a.jchunk, Np) - ks * a.jchunk) / 32;
+  const bf16x8* __restrict__ Kb = reinterpret_cast<const bf16x8*>(a.Kt) + ((size_t)rb * (Np / 32) + c0) * 256 + lane;
+  const bf16x8* __restrict__ Qb =
+      reinterpret_cast<const bf16x8*>(a.q_in + (size_t)b * NS * kLP * Np) + (size_t)c0 * NS * 128 + lane;
+  auto load_k = [&](int st_, int t) { return Kb[((size_t)st_ * 4 + t) * 64]; };
+  auto load_q = [&](int st_, int p, int half) { return Qb[((size_t)st_ * NS * 2 + p * 2 + half) * 64]; };
   f32x4 acc[4][2];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t][0] = acc[t][1] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -156,13 +181,12 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
     bf16x8 av[U][4], bq[U][NS][2];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j0 = jb + 32 * (st + 4 * u);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) av[u][t] = load_k(t, j0 + kq);
+      for (int t = 0; t < 4; ++t) av[u][t] = load_k(st + 4 * u, t);
 #pragma unroll
       for (int p = 0; p < NS; ++p) {
-        bq[u][p][0] = load_q(j0, p, 0);
-        bq[u][p][1] = load_q(j0, p, 1);
+        bq[u][p][0] = load_q(st + 4 * u, p, 0);
+        bq[u][p][1] = load_q(st + 4 * u, p, 1);
       }
     }
 #pragma unroll
@@ -176,13 +200,12 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
         }
   }
   for (; st < nst; st += 4) {
-    const int j0 = jb + 32 * st;
     bf16x8 av[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) av[t] = load_k(t, j0 + kq);
+    for (int t = 0; t < 4; ++t) av[t] = load_k(st, t);
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
-      const bf16x8 b0 = load_q(j0, p, 0), b1 = load_q(j0, p, 1);
+      const bf16x8 b0 = load_q(st, p, 0), b1 = load_q(st, p, 1);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], b0, acc[t][0], 0, 0, 0);
@@ -224,8 +247,11 @@ constexpr int kTParts = kEpiThreads / kLP;
 template <int NS, int COMPAT, bool COOC, int LC>
 __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepArgs a, float one_minus_alpha) {
   const int rb = blockIdx.x, b = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // label group, uniform in the wavefront
   const int L = LC > 0 ? LC : a.L, N = a.N, Np = a.Np;
+  __shared__ float Th[kLP * kLP];      // Theta (general), rows of stride 32
+  __shared__ float Cc[kLP * kLP];      // co-occurrence
   __shared__ float St[kRB * kSt];      // S[node][label]
   __shared__ float Qt[kRB * kSt];      // q[node][label] (co-occurrence)
   __shared__ float red[4 * kRB];       // per-node partials of the four label groups
@@ -244,6 +270,10 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
     ell[j] = on ? a.state_in[base + (size_t)l * N] : 0.f;
     un[j] = on ? a.unary[base + (size_t)l * N] : 0.f;
   }
+  if (COMPAT != MF_COMPAT_POTTS)
+    for (int f = tid; f < L * L; f += kEpiThreads) Th[(f / L) * kLP + f % L] = a.theta[f];
+  if (COOC)
+    for (int f = tid; f < L * L; f += kEpiThreads) Cc[(f / L) * kLP + f % L] = a.cooc[f];
   if (COOC) {
     // column sums: label tid % 32, blocks tid / 32 + 8 k in order
     const int l = tid % kLP;
@@ -258,7 +288,7 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
     float acc[kRB * kLP / kEpiThreads];
 #pragma unroll
     for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) acc[r] = 0.f;
-#pragma unroll 4
+#pragma unroll 8
     for (int k = 0; k < a.KS; ++k) {
 #pragma unroll
       for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) acc[r] += sp[(size_t)k * Np * kLP + tid + r * kEpiThreads];
@@ -313,9 +343,9 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
         float acc = 0.f;
         if constexpr (LC > 0) {
 #pragma unroll
-          for (int k = 0; k < LC; ++k) acc = fmaf(a.theta[l * LC + k], srow[k], acc);
+          for (int k = 0; k < LC; ++k) acc = fmaf(Th[l * kLP + k], srow[k], acc);
         } else {
-          for (int k = 0; k < L; ++k) acc = fmaf(a.theta[l * L + k], St[lane * kSt + k], acc);
+          for (int k = 0; k < L; ++k) acc = fmaf(Th[l * kLP + k], St[lane * kSt + k], acc);
         }
         m += acc;
       }
@@ -323,9 +353,9 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
         float c = 0.f;
         if constexpr (LC > 0) {
 #pragma unroll
-          for (int k = 0; k < LC; ++k) c = fmaf(a.cooc[l * LC + k], qrow[k], c);
+          for (int k = 0; k < LC; ++k) c = fmaf(Cc[l * kLP + k], qrow[k], c);
         } else {
-          for (int k = 0; k < L; ++k) c = fmaf(a.cooc[l * L + k], Ts[k] - Qt[lane * kSt + k], c);
+          for (int k = 0; k < L; ++k) c = fmaf(Cc[l * kLP + k], Ts[k] - Qt[lane * kSt + k], c);
         }
         m += c * a.inv_n;
       }
@@ -357,9 +387,11 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
     const int l = w + 4 * j;
     const float q = inside ? e[j] * inv : 0.f;
     if (inside && l < L) a.state_out[base + (size_t)l * N] = z[j] - lse;
-    store_planes<NS>(planes, Np, l, i, q);
-    const float t = wave_sum_f(q);
-    if (lane == 0) a.t_out[((size_t)b * a.NRB + rb) * kLP + l] = t;
+    store_planes<NS>(planes, l, i, q);
+    if (COOC) {
+      const float t = wave_sum_dpp(q);
+      if (lane == 0) a.t_out[((size_t)b * a.NRB + rb) * kLP + l] = t;
+    }
   }
 }
 
@@ -455,10 +487,7 @@ hipError_t epilogue_lc(const DenseStepArgs& a, int compat, float om, hipStream_t
 
 template <int NS>
 hipError_t step_ns(const DenseStepArgs& a, int compat, hipStream_t s) {
-  if (a.N % 8 == 0)
-    hipLaunchKernelGGL((dense_step_kernel<NS, true>), dim3(a.NRB * a.KS, a.B), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((dense_step_kernel<NS, false>), dim3(a.NRB * a.KS, a.B), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((dense_step_kernel<NS>), dim3(a.NRB * a.KS, a.B), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const float om = (float)(1.0 - (double)a.alpha);
@@ -483,6 +512,13 @@ DenseGeometry dense_geometry(int N, int B) {
   g.jchunk = (chunks + ks - 1) / ks * 32;
   g.KS = (g.Np + g.jchunk - 1) / g.jchunk;
   return g;
+}
+
+hipError_t launch_dense_tile_k(const DenseStepArgs& a, hipStream_t s) {
+  const size_t chunks = (size_t)a.Np * (a.Np / 8);
+  hipLaunchKernelGGL(dense_tile_k_kernel, dim3((unsigned)((chunks + 255) / 256)), dim3(256), 0, s, a.K, a.N, a.Np,
+                     reinterpret_cast<bf16x8*>(a.Kt));
+  return hipGetLastError();
 }
 
 hipError_t launch_dense_kernel(const float* f, int n, int dim, uint16_t* K, hipStream_t s) {

@@ -60,6 +60,8 @@ mf::WorkspaceLayout layout_for(const mf_desc& d) {
     const size_t Np = (size_t)w.dg.Np;
     w.dq = off;
     off += align256(sizeof(uint16_t) * 2 * B * (size_t)w.dense_ns * 32 * Np);
+    w.dk = off;
+    off += align256(sizeof(uint16_t) * Np * Np);
     w.ds = off;
     off += align256(sizeof(float) * B * (size_t)w.dg.KS * Np * 32);
     w.dt = off;
@@ -176,6 +178,7 @@ mf::DenseStepArgs dense_args(const mf_handle* h, int from) {
   const size_t elems = B * d.n_labels * d.n_nodes;
   mf::DenseStepArgs a;
   a.K = d.dense_K;
+  a.Kt = (uint16_t*)ws_at(h, w.dk);
   a.unary = d.unary;
   a.state_in = d.state + (size_t)from * elems;
   a.state_out = d.state + (size_t)(from ^ 1) * elems;
@@ -263,6 +266,8 @@ mf_status enqueue_init(mf_handle* h, bool clear_flags) {
     // planes and column sums of q^0 go to slot 0: prepare writes the "out" side of from = 1
     mf::DenseStepArgs a = dense_args(h, 1);
     a.state_in = buf(h, 0);
+    e = mf::launch_dense_tile_k(a, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("dense K tiling launch: ") + hipGetErrorString(e));
     e = mf::launch_dense_prepare(a, h->ws.dense_ns, h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("dense prepare launch: ") + hipGetErrorString(e));
   }

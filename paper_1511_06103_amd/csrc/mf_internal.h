@@ -76,11 +76,13 @@ struct CsrFreeEnergyArgs {
 };
 
 struct DenseStepArgs {
-  const uint16_t* K;       // [N][N] bf16 bits
+  const uint16_t* K;       // [N][N] bf16 bits, row-major (the caller's)
+  uint16_t* Kt;            // the same K zero-padded to Np x Np in MFMA operand order:
+                           // [Np/64][Np/32][4][64 lanes][8]
   const float* unary;      // [B][L][N]
   const float* state_in;   // [B][L][N]
   float* state_out;
-  const uint16_t* q_in;    // [B][NS][32][Np] bf16 planes of q(state_in)
+  const uint16_t* q_in;    // [B][Np/32][NS][2][64 lanes][8] bf16 planes of q(state_in)
   uint16_t* q_out;         // planes of q(state_out)
   float* s_part;           // [B][KS][Np][32] partial S
   const float* t_in;       // [B][NRB][32] column sums of q(state_in) per row block
@@ -158,7 +160,8 @@ struct WorkspaceLayout {
   size_t partials = 0;     // double[B][n_blocks]
   size_t f_out = 0;        // double[B]
   size_t csr_q = 0;        // float[2][B][N][LQ] (CSR only)
-  size_t dq = 0;           // uint16[2][B][NS][32][Np] q planes (dense only)
+  size_t dq = 0;           // uint16[2][B][NS * 32 * Np] q planes (dense only)
+  size_t dk = 0;           // uint16[Np * Np] K in MFMA operand order
   size_t ds = 0;           // float[B][KS][Np][32] partial S
   size_t dt = 0;           // float[2][B][NRB][32] column sums
   size_t dqd = 0;          // double[B][N][L] free-energy scratch
@@ -191,6 +194,7 @@ hipError_t launch_dense_kernel(const float* f, int n, int dim, uint16_t* K, hipS
 int dense_planes(int precision);
 DenseGeometry dense_geometry(int N, int B);
 hipError_t launch_dense_prepare(const DenseStepArgs& a, int NS, hipStream_t s);
+hipError_t launch_dense_tile_k(const DenseStepArgs& a, hipStream_t s);
 hipError_t launch_dense_step(const DenseStepArgs& a, int NS, int compat, hipStream_t s);
 hipError_t launch_dense_free_energy(const DenseFreeEnergyArgs& a, int compat, hipStream_t s);
 
