@@ -11,7 +11,10 @@
 // kernel B the transposed stencil over Sb (needs the Sb halo) and the new g.
 // Theta_bar partials are per tile: mb and S of the tile's nodes are staged in
 // LDS and the L x L block product is formed there on the FP32 matrix cores,
-// then reduced over tiles in a fixed order into an FP64 accumulator.
+// then added to the tile's own FP64 accumulator (each workgroup owns its
+// slot, so there is no race).  After the last step the tile accumulators
+// are reduced in a fixed order: the sum runs over steps within a tile, then
+// over tiles, and is deterministic.
 #include <hip/hip_runtime.h>
 
 #include "mf_internal.h"
@@ -46,7 +49,11 @@ __device__ __forceinline__ void load_halo(const float* __restrict__ src, float* 
     const int hy = r / AX, hx = r - (r / AX) * AX;
     const int gy = y0 + hy - 1, gx = x0 + hx - 1;
     const bool on = l < L && gy >= 0 && gy < H && gx >= 0 && gx < W;
-    v[it] = on ? src[(size_t)l * N + gy * W + gx] : (EXP ? -INFINITY : 0.f);
+    // clamped address: the load is unconditional, the value selected
+    const int lc = l < L ? l : L - 1;
+    const int gyc = gy < 0 ? 0 : (gy < H ? gy : H - 1), gxc = gx < 0 ? 0 : (gx < W ? gx : W - 1);
+    const float t = src[(size_t)lc * N + gyc * W + gxc];
+    v[it] = on ? t : (EXP ? -INFINITY : 0.f);
   }
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -69,7 +76,24 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
   const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
   const size_t base = (size_t)b * L * N;
   const int tid = threadIdx.x;
+  const int tx = tid % kTileX, ty = tid / kTileX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool inside = x < W && y < H;
+  const int n = inside ? y * W + x : 0;
+  const int p = (ty + 1) * AX + (tx + 1);
 
+  // every load of the node is issued before any store: the output planes may
+  // alias nothing the kernel reads, but the compiler cannot know that
+  float g[LP], q1[LP], ub[LP];
+#pragma unroll
+  for (int l = 0; l < LP; ++l) {
+    const bool on = inside && l < L;
+    const size_t at = base + (size_t)(l < L ? l : L - 1) * N + n;
+    const float g_ = a.g_in[at], q_ = a.ell_t1[at], u_ = a.u_bar[at];
+    g[l] = on ? g_ : 0.f;
+    q1[l] = on ? q_ : 0.f;
+    ub[l] = on ? u_ : 0.f;
+  }
   load_halo<LP, true>(a.ell_t + base, qs, L, N, H, W, x0, y0, tid);
   if (COMPAT == MF_COMPAT_GENERAL) {
 #pragma unroll
@@ -80,12 +104,6 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
   }
   __syncthreads();
 
-  const int tx = tid % kTileX, ty = tid / kTileX;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool inside = x < W && y < H;
-  const int n = inside ? y * W + x : 0;
-  const int p = (ty + 1) * AX + (tx + 1);
-
   float mb[LP], S[LP];
 #pragma unroll
   for (int l = 0; l < LP; ++l) {
@@ -93,19 +111,14 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
     S[l] = 0.f;
   }
   if (inside) {
-    float g[LP];
     float sg = 0.f;
 #pragma unroll
-    for (int l = 0; l < LP; ++l) {
-      g[l] = (l < L) ? a.g_in[base + (size_t)l * N + n] : 0.f;
-      sg += g[l];
-    }
+    for (int l = 0; l < LP; ++l) sg += g[l];
 #pragma unroll
     for (int l = 0; l < LP; ++l) {
       if (l < L) {
-        const float q1 = __expf(a.ell_t1[base + (size_t)l * N + n]);
-        mb[l] = -a.alpha * (g[l] - q1 * sg);
-        a.u_bar[base + (size_t)l * N + n] += mb[l];
+        mb[l] = -a.alpha * (g[l] - __expf(q1[l]) * sg);
+        a.u_bar[base + (size_t)l * N + n] = ub[l] + mb[l];
         const float* q = qs + l * AN + p;
         float s = q[-AX] + q[-1] + q[1] + q[AX];
         if (CONN == 8) s += (q[-AX - 1] + q[-AX + 1]) + (q[AX - 1] + q[AX + 1]);
@@ -159,12 +172,12 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
     }
     const size_t part = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    float* out = a.theta_part + part * L * L;
+    double* out = a.theta_tile + part * L * L;
     if constexpr (WPB == 1) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int l = 16 * rb + 4 * (lane >> 4) + i;
-        if (l < L && kc < L) out[l * L + kc] = acc[i];
+        if (l < L && kc < L) out[l * L + kc] += (double)acc[i];
       }
     } else {
 #pragma unroll
@@ -176,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
           const float v = ((red[lane * 4 + i] + red[256 + lane * 4 + i]) + red[512 + lane * 4 + i]) +
                           red[768 + lane * 4 + i];
           const int l = 4 * (lane >> 4) + i;
-          if (l < L && kc < L) out[l * L + kc] = v;
+          if (l < L && kc < L) out[l * L + kc] += (double)v;
         }
       }
     }
@@ -192,51 +205,59 @@ __global__ __launch_bounds__(kThreads) void adj_b_kernel(AdjointArgs a) {
   const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
   const size_t base = (size_t)b * L * N;
   const int tid = threadIdx.x;
-  load_halo<LP, false>(a.s_bar + base, sb, L, N, H, W, x0, y0, tid);
-  __syncthreads();
   const int tx = tid % kTileX, ty = tid / kTileX;
   const int x = x0 + tx, y = y0 + ty;
-  if (x >= W || y >= H) return;
-  const int n = y * W + x;
+  const bool inside = x < W && y < H;
+  const int n = inside ? y * W + x : 0;
   const int p = (ty + 1) * AX + (tx + 1);
-  float g[LP];
-  float sg = 0.f;
+  load_halo<LP, false>(a.s_bar + base, sb, L, N, H, W, x0, y0, tid);
+  __syncthreads();
+  if (!inside) return;
+  // the node's loads first, then the stores
+  float g[LP], l1[LP], l0[LP];
 #pragma unroll
   for (int l = 0; l < LP; ++l) {
-    g[l] = (l < L) ? a.g_in[base + (size_t)l * N + n] : 0.f;
-    sg += g[l];
+    const size_t at = base + (size_t)(l < L ? l : L - 1) * N + n;
+    g[l] = a.g_in[at];
+    l1[l] = a.ell_t1[at];
+    l0[l] = a.ell_t[at];
+    if (l >= L) g[l] = 0.f;
   }
+  float sg = 0.f;
+#pragma unroll
+  for (int l = 0; l < LP; ++l) sg += g[l];
   const float om = 1.f - a.alpha;
 #pragma unroll
   for (int l = 0; l < LP; ++l) {
     if (l < L) {
-      const float q1 = __expf(a.ell_t1[base + (size_t)l * N + n]);
-      const float zb = g[l] - q1 * sg;
+      const float zb = g[l] - __expf(l1[l]) * sg;
       const float* s = sb + l * AN + p;
       float qb = s[-AX] + s[-1] + s[1] + s[AX];
       if (CONN == 8) qb += (s[-AX - 1] + s[-AX + 1]) + (s[AX - 1] + s[AX + 1]);
-      const float q0 = __expf(a.ell_t[base + (size_t)l * N + n]);
-      a.g_out[base + (size_t)l * N + n] = om * zb + q0 * qb;
+      a.g_out[base + (size_t)l * N + n] = om * zb + __expf(l0[l]) * qb;
     }
   }
 }
 
-// theta_acc[e] += sum over tiles of theta_part[tile][e] in FP64, in a fixed
+// theta_acc[e] = sum over tiles of theta_tile[tile][e] in FP64, in a fixed
 // order: stage 1, block c sums tiles [32 c, 32 c + 32) (loads coalesced over
 // e); stage 2 adds the stage-1 sums in block order.
-__global__ __launch_bounds__(256) void adj_theta_stage(const float* __restrict__ part, int n_parts, int LL,
+__global__ __launch_bounds__(256) void adj_theta_stage(const double* __restrict__ part, int n_parts, int LL,
                                                        double* __restrict__ stage) {
   const int c = blockIdx.x;
   const int k0 = c * kThetaChunk;
   const int k1 = k0 + kThetaChunk < n_parts ? k0 + kThetaChunk : n_parts;
   for (int e = threadIdx.x; e < LL; e += 256) {
     // fixed order; the loads of the chunk are issued before the adds
-    float v[kThetaChunk];
+    double v[kThetaChunk];
 #pragma unroll
-    for (int k = 0; k < kThetaChunk; ++k) v[k] = k0 + k < k1 ? part[(size_t)(k0 + k) * LL + e] : 0.f;
+    for (int k = 0; k < kThetaChunk; ++k) {
+      const double t = part[(size_t)(k0 + k < k1 ? k0 + k : k1 - 1) * LL + e];   // clamped: no branch
+      v[k] = k0 + k < k1 ? t : 0.0;
+    }
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < kThetaChunk; ++k) s += (double)v[k];
+    for (int k = 0; k < kThetaChunk; ++k) s += v[k];
     stage[(size_t)c * LL + e] = s;
   }
 }
@@ -248,7 +269,7 @@ __global__ __launch_bounds__(256) void adj_theta_finish(const double* __restrict
   double s = 0.0;
 #pragma unroll 16
   for (int c = 0; c < n_stage; ++c) s += stage[(size_t)c * LL + e];
-  acc[e] += s;
+  acc[e] = s;
 }
 
 // Through the initialisation log q0 = -u - lse(-u): ub += -(g0 - q0 sum g0).
@@ -298,16 +319,6 @@ hipError_t adj_lp(const AdjointArgs& a, int conn, int compat, hipStream_t s) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int n_parts = (int)(grid.x * grid.y * grid.z);
-  const int LL = a.L * a.L;
-  const int n_stage = (n_parts + kThetaChunk - 1) / kThetaChunk;
-  hipLaunchKernelGGL(adj_theta_stage, dim3(n_stage), dim3(256), 0, s, a.theta_part, n_parts, LL, a.theta_stage);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_theta_finish, dim3((LL + 255) / 256), dim3(256), 0, s, a.theta_stage, n_stage, LL,
-                     a.theta_acc);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (conn == 4) hipLaunchKernelGGL((adj_b_kernel<LP, EXACT, 4>), grid, dim3(kThreads), 0, s, a);
   else hipLaunchKernelGGL((adj_b_kernel<LP, EXACT, 8>), grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
@@ -331,6 +342,18 @@ hipError_t launch_adjoint_step(const AdjointArgs& a, int conn, int compat, hipSt
   if (L <= 8) return adj_lp<8, false>(a, conn, compat, s);
   if (L <= 16) return adj_lp<16, false>(a, conn, compat, s);
   return adj_lp<32, false>(a, conn, compat, s);
+}
+
+hipError_t launch_adjoint_theta_reduce(const AdjointArgs& a, hipStream_t s) {
+  const int n_parts = (int)adjoint_theta_parts(a.B, a.H, a.W);
+  const int LL = a.L * a.L;
+  const int n_stage = (n_parts + kThetaChunk - 1) / kThetaChunk;
+  hipLaunchKernelGGL(adj_theta_stage, dim3(n_stage), dim3(256), 0, s, a.theta_tile, n_parts, LL, a.theta_stage);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_theta_finish, dim3((LL + 255) / 256), dim3(256), 0, s, a.theta_stage, n_stage, LL,
+                     a.theta_acc);
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint_init(const float* g0, const float* ell0, float* u_bar, int B, int L, int N, hipStream_t s) {

@@ -624,7 +624,7 @@ size_t mf_backward_workspace_size(const mf_handle* h, int32_t ckpt_every) {
   off += align256(sizeof(float) * E * ((size_t)ckpt_every + 1));   // recomputed states
   off += align256(sizeof(float) * E * 2);                          // gradient ping-pong
   off += align256(sizeof(float) * E);                              // Theta^T m_bar
-  off += align256(sizeof(float) * LL * mf::adjoint_theta_parts(d.batch, d.height, d.width));
+  off += align256(sizeof(double) * LL * mf::adjoint_theta_parts(d.batch, d.height, d.width));
   off += align256(sizeof(double) * LL);
   off += align256(sizeof(double) * LL * mf::adjoint_theta_stages(d.batch, d.height, d.width));
   return off;
@@ -654,8 +654,9 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
   w += align256(sizeof(float) * E * 2);
   float* Sb = (float*)w;
   w += align256(sizeof(float) * E);
-  float* part = (float*)w;
-  w += align256(sizeof(float) * LL * mf::adjoint_theta_parts(d.batch, d.height, d.width));
+  const size_t n_parts = mf::adjoint_theta_parts(d.batch, d.height, d.width);
+  double* part = (double*)w;
+  w += align256(sizeof(double) * LL * n_parts);
   double* acc = (double*)w;
   w += align256(sizeof(double) * LL);
   double* stage = (double*)w;
@@ -665,6 +666,7 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
     return fail(h, MF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
   };
   hipError_t e = mf::launch_fill_f32(grad_unary, E, 0.f, s);
+  if (e == hipSuccess) e = mf::launch_fill_f64(part, LL * n_parts, s);
   if (e == hipSuccess) e = mf::launch_fill_f64(acc, LL, s);
   if (e == hipSuccess) e = mf::launch_copy_f32(grad_logq_T, G, E, s);
   if (e != hipSuccess) return dev_fail(e, "backward setup");
@@ -700,7 +702,7 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
       a.u_bar = grad_unary;
       a.s_bar = Sb;
       a.theta = d.theta;
-      a.theta_part = part;
+      a.theta_tile = part;
       a.theta_stage = stage;
       a.theta_acc = acc;
       a.B = d.batch;
@@ -718,6 +720,18 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
   if (d.init == MF_INIT_UNARY) {
     e = mf::launch_adjoint_init(G + (size_t)gc * E, ckpt_states, grad_unary, d.batch, d.n_labels, d.n_nodes, s);
     if (e != hipSuccess) return dev_fail(e, "init adjoint");
+  }
+  {
+    mf::AdjointArgs a;
+    a.theta_tile = part;
+    a.theta_stage = stage;
+    a.theta_acc = acc;
+    a.B = d.batch;
+    a.L = d.n_labels;
+    a.H = d.height;
+    a.W = d.width;
+    e = mf::launch_adjoint_theta_reduce(a, s);
+    if (e != hipSuccess) return dev_fail(e, "theta reduction");
   }
   e = mf::launch_f64_to_f32(acc, grad_theta, LL, s);
   if (e != hipSuccess) return dev_fail(e, "theta gradient");

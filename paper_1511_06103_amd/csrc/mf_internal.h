@@ -147,9 +147,9 @@ struct AdjointArgs {
   float* u_bar;            // [B][L][N] accumulated
   float* s_bar;            // [B][L][N] scratch: Theta^T m_bar
   const float* theta;
-  float* theta_part;       // [parts][L][L]
-  double* theta_stage;     // [stages][L][L] FP64 sums of 32 tile partials each
-  double* theta_acc;       // [L][L] accumulated
+  double* theta_tile;      // [parts][L][L] per-tile FP64 sums over the steps so far
+  double* theta_stage;     // [stages][L][L] FP64 sums of 32 tile sums each
+  double* theta_acc;       // [L][L] the gradient, written once at the end
   int B, L, N, H, W;
   float alpha, potts_w;
 };
@@ -210,6 +210,8 @@ hipError_t launch_csr_free_energy(const CsrFreeEnergyArgs& a, int compat, hipStr
 size_t adjoint_theta_parts(int B, int H, int W);
 size_t adjoint_theta_stages(int B, int H, int W);
 hipError_t launch_adjoint_step(const AdjointArgs& a, int conn, int compat, hipStream_t s);
+// theta_acc = sum over tiles of theta_tile, in a fixed order (after the last step).
+hipError_t launch_adjoint_theta_reduce(const AdjointArgs& a, hipStream_t s);
 hipError_t launch_adjoint_init(const float* g0, const float* ell0, float* u_bar, int B, int L, int N,
                                hipStream_t s);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
