@@ -60,88 +60,152 @@ __global__ __launch_bounds__(kCsrThreads) void csr_q_from_state_kernel(const flo
   for (int k = 0; k < LQ / 4; ++k) dst[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
 }
 
-template <int LQ, bool EXACT, int COMPAT>
+// Partner lane of a node (P = 2): lanes 2n and 2n + 1 swap a value (DPP
+// quad permutation 1, 0, 3, 2).
+__device__ inline float partner(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// P lanes per node (P = 1 or 2): lane h of a node holds labels
+// [h LH, h LH + LH), LH = LQ / P, and gathers that part of each neighbour's
+// q row; the halves of S, the max and the sum are exchanged with the partner
+// lane in a fixed order, so both lanes hold bitwise the same values.  Two
+// lanes per node double the wavefronts in flight, which hides the latency of
+// the dependent row_ptr -> col -> q loads.  LC > 0: L == LC at compile
+// time.  Theta is staged in LDS zero-padded to LQ x LQ, so the message needs
+// no per-label test for any L; padded labels carry z = -inf (q = 0).
+template <int LQ, int LC, int COMPAT, int P>
 __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, float one_minus_alpha) {
-  const int L = EXACT ? LQ : a.L;
+  constexpr int LH = LQ / P;
+  static_assert(LH % 4 == 0, "each lane gathers whole float4 slices");
+  __shared__ float Th[COMPAT == MF_COMPAT_GENERAL ? LQ * LQ : 1];
+  const int L = LC > 0 ? LC : a.L;
   const int N = a.N;
-  const int i = blockIdx.x * kCsrThreads + threadIdx.x;
+  const int t = blockIdx.x * kCsrThreads + threadIdx.x;
+  const int i = t / P, h = P == 1 ? 0 : (t & 1);
   const int b = blockIdx.y;
-  if (i >= N) return;
+  if (COMPAT == MF_COMPAT_GENERAL) {
+    for (int f = threadIdx.x; f < LQ * LQ; f += kCsrThreads) {
+      const int l = f / LQ, k = f - (f / LQ) * LQ;
+      Th[f] = (l < L && k < L) ? a.theta[l * L + k] : 0.f;
+    }
+    __syncthreads();
+  }
+  if (i >= N) return;   // both lanes of a node leave together
   const size_t base = (size_t)b * L * N;
   const float* __restrict__ li = a.state_in + base + i;
   const float* __restrict__ ui = a.unary + base + i;
+  const int l0 = h * LH;
 
-  float ell[LQ], uu[LQ];
+  float ell[LH], uu[LH];
 #pragma unroll
-  for (int l = 0; l < LQ; ++l) {
-    ell[l] = (l < L) ? li[(size_t)l * N] : 0.f;
-    uu[l] = (l < L) ? ui[(size_t)l * N] : 0.f;
+  for (int u = 0; u < LH; ++u) {
+    const int l = l0 + u;
+    const size_t at = (size_t)(l < L ? l : L - 1) * N;   // clamped: no branch
+    const float x = li[at], y = ui[at];
+    ell[u] = l < L ? x : 0.f;
+    uu[u] = l < L ? y : 0.f;
   }
 
-  float S[LQ];
+  float S[LH];
 #pragma unroll
-  for (int l = 0; l < LQ; ++l) S[l] = 0.f;
-  const float4* __restrict__ qb = reinterpret_cast<const float4*>(a.q_in + (size_t)b * N * LQ);
+  for (int u = 0; u < LH; ++u) S[u] = 0.f;
+  const float4* __restrict__ qb = reinterpret_cast<const float4*>(a.q_in + (size_t)b * N * LQ) + h * (LH / 4);
   // Clamp the row to [0, nnz) and skip out-of-range columns: a malformed CSR
   // (reported through the flags by csr_check_kernel) never reads out of bounds.
   long long e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
   e0 = e0 < 0 ? 0 : e0;
   e1 = e1 > a.nnz ? a.nnz : e1;
-  for (long long e = e0; e < e1; ++e) {
-    const int j = a.col[e];
-    if (j < 0 || j >= N) continue;
-    const float w = a.w ? a.w[e] : 1.f;
-    const float4* qj = qb + (size_t)j * (LQ / 4);
+  // EB edges per trip: their column indices, then their q rows, are loaded
+  // together.  Edges past the row end (and out-of-range columns) get weight
+  // 0 and a valid address; the products are added in edge order.
+  constexpr int EB = 4;
+  for (long long e = e0; e < e1; e += EB) {
+    int j[EB];
+    float w[EB];
 #pragma unroll
-    for (int k = 0; k < LQ / 4; ++k) {
-      const float4 v = qj[k];
-      S[4 * k] = fmaf(w, v.x, S[4 * k]);
-      S[4 * k + 1] = fmaf(w, v.y, S[4 * k + 1]);
-      S[4 * k + 2] = fmaf(w, v.z, S[4 * k + 2]);
-      S[4 * k + 3] = fmaf(w, v.w, S[4 * k + 3]);
+    for (int u = 0; u < EB; ++u) {
+      const bool on = e + u < e1;
+      const long long ec = on ? e + u : e0;
+      const int jj = a.col[ec];
+      const float ww = a.w ? a.w[ec] : 1.f;
+      const bool ok = on && jj >= 0 && jj < N;
+      j[u] = ok ? jj : 0;
+      w[u] = ok ? ww : 0.f;
+    }
+    float4 v[EB][LH / 4];
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const float4* qj = qb + (size_t)j[u] * (LQ / 4);
+#pragma unroll
+      for (int k = 0; k < LH / 4; ++k) v[u][k] = qj[k];
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+#pragma unroll
+      for (int k = 0; k < LH / 4; ++k) {
+        S[4 * k] = fmaf(w[u], v[u][k].x, S[4 * k]);
+        S[4 * k + 1] = fmaf(w[u], v[u][k].y, S[4 * k + 1]);
+        S[4 * k + 2] = fmaf(w[u], v[u][k].z, S[4 * k + 2]);
+        S[4 * k + 3] = fmaf(w[u], v[u][k].w, S[4 * k + 3]);
+      }
     }
   }
 
-  float z[LQ];
+  // S of all LQ labels in label order: own half and the partner's
+  float Sa[LQ];
+#pragma unroll
+  for (int u = 0; u < LH; ++u) {
+    if constexpr (P == 1) {
+      Sa[u] = S[u];
+    } else {
+      const float o = partner(S[u]);
+      Sa[u] = h == 0 ? S[u] : o;
+      Sa[LH + u] = h == 0 ? o : S[u];
+    }
+  }
+  float z[LH];
   if (COMPAT == MF_COMPAT_POTTS) {
     float tot = 0.f;
 #pragma unroll
-    for (int l = 0; l < LQ; ++l) tot += S[l];
+    for (int k = 0; k < LQ; ++k) tot += Sa[k];
 #pragma unroll
-    for (int l = 0; l < LQ; ++l) z[l] = one_minus_alpha * ell[l] - a.alpha * (uu[l] + a.potts_w * (tot - S[l]));
+    for (int u = 0; u < LH; ++u) z[u] = one_minus_alpha * ell[u] - a.alpha * (uu[u] + a.potts_w * (tot - S[u]));
   } else {
-    const float* __restrict__ th = a.theta;
 #pragma unroll
-    for (int l = 0; l < LQ; ++l) {
+    for (int u = 0; u < LH; ++u) {
       float acc = 0.f;
-      if (l < L) {
 #pragma unroll
-        for (int k = 0; k < LQ; ++k)
-          if (k < L) acc = fmaf(th[l * L + k], S[k], acc);
-      }
-      z[l] = one_minus_alpha * ell[l] - a.alpha * (uu[l] + acc);
+      for (int k = 0; k < LQ; ++k) acc = fmaf(Th[(l0 + u) * LQ + k], Sa[k], acc);
+      z[u] = one_minus_alpha * ell[u] - a.alpha * (uu[u] + acc);
     }
   }
-  float mx = -INFINITY;
 #pragma unroll
-  for (int l = 0; l < LQ; ++l)
-    if (l < L) mx = fmaxf(mx, z[l]);
-  float e[LQ];
+  for (int u = 0; u < LH; ++u) z[u] = l0 + u < L ? z[u] : -INFINITY;
+  float mx = z[0];
+#pragma unroll
+  for (int u = 1; u < LH; ++u) mx = fmaxf(mx, z[u]);
+  if constexpr (P == 2) mx = fmaxf(mx, partner(mx));
+  float e[LH];
   float se = 0.f;
 #pragma unroll
-  for (int l = 0; l < LQ; ++l) {
-    e[l] = (l < L) ? __expf(z[l] - mx) : 0.f;
-    se += e[l];
+  for (int u = 0; u < LH; ++u) {
+    e[u] = __expf(z[u] - mx);
+    se += e[u];
+  }
+  if constexpr (P == 2) {
+    const float o = partner(se);
+    se = h == 0 ? se + o : o + se;   // the lower half first in both lanes
   }
   const float lse = mx + __logf(se);
   const float inv = 1.0f / se;
   float* __restrict__ out = a.state_out + base + i;
 #pragma unroll
-  for (int l = 0; l < LQ; ++l)
-    if (l < L) out[(size_t)l * N] = z[l] - lse;
-  float4* qo = reinterpret_cast<float4*>(a.q_out + ((size_t)b * N + i) * LQ);
+  for (int u = 0; u < LH; ++u)
+    if (l0 + u < L) out[(size_t)(l0 + u) * N] = z[u] - lse;
+  float4* qo = reinterpret_cast<float4*>(a.q_out + ((size_t)b * N + i) * LQ) + h * (LH / 4);
 #pragma unroll
-  for (int k = 0; k < LQ / 4; ++k)
+  for (int k = 0; k < LH / 4; ++k)
     qo[k] = make_float4(e[4 * k] * inv, e[4 * k + 1] * inv, e[4 * k + 2] * inv, e[4 * k + 3] * inv);
 }
 
@@ -210,14 +274,15 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
   if (threadIdx.x == 0) a.partials[(size_t)b * a.n_blocks + blockIdx.x] = t;
 }
 
-template <int LQ, bool EXACT>
+template <int LQ, int LC>
 hipError_t csr_step_lq(const CsrStepArgs& a, int compat, hipStream_t s) {
-  dim3 grid((a.N + kCsrThreads - 1) / kCsrThreads, a.B);
+  constexpr int P = LQ >= 16 ? 2 : 1;
+  dim3 grid((unsigned)(((size_t)a.N * P + kCsrThreads - 1) / kCsrThreads), a.B);
   const float om = (float)(1.0 - (double)a.alpha);
   if (compat == MF_COMPAT_POTTS)
-    hipLaunchKernelGGL((csr_step_kernel<LQ, EXACT, MF_COMPAT_POTTS>), grid, dim3(kCsrThreads), 0, s, a, om);
+    hipLaunchKernelGGL((csr_step_kernel<LQ, LC, MF_COMPAT_POTTS, P>), grid, dim3(kCsrThreads), 0, s, a, om);
   else
-    hipLaunchKernelGGL((csr_step_kernel<LQ, EXACT, MF_COMPAT_GENERAL>), grid, dim3(kCsrThreads), 0, s, a, om);
+    hipLaunchKernelGGL((csr_step_kernel<LQ, LC, MF_COMPAT_GENERAL, P>), grid, dim3(kCsrThreads), 0, s, a, om);
   return hipGetLastError();
 }
 
@@ -230,7 +295,9 @@ hipError_t csr_q_lq(const float* state, float* qn, int B, int L, int N, hipStrea
 
 }  // namespace
 
-int csr_label_stride(int L) { return (L + 3) & ~3; }
+// Node-major q row length: L rounded up to 4 (L <= 12) or to 8 (two lanes
+// per node, each gathering whole float4 slices).
+int csr_label_stride(int L) { return L <= 12 ? (L + 3) & ~3 : (L + 7) & ~7; }
 
 hipError_t launch_csr_check(const int* row_ptr, const int* col, int N, long long nnz, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(csr_check_kernel, dim3((N + 1 + kCsrThreads - 1) / kCsrThreads), dim3(kCsrThreads), 0, s,
@@ -244,23 +311,19 @@ hipError_t launch_csr_q_from_state(const float* state, float* qn, int B, int L, 
     case 8: return csr_q_lq<8>(state, qn, B, L, N, s);
     case 12: return csr_q_lq<12>(state, qn, B, L, N, s);
     case 16: return csr_q_lq<16>(state, qn, B, L, N, s);
-    case 20: return csr_q_lq<20>(state, qn, B, L, N, s);
     case 24: return csr_q_lq<24>(state, qn, B, L, N, s);
-    case 28: return csr_q_lq<28>(state, qn, B, L, N, s);
     default: return csr_q_lq<32>(state, qn, B, L, N, s);
   }
 }
 
 hipError_t launch_csr_step(const CsrStepArgs& a, int compat, hipStream_t s) {
   switch (csr_label_stride(a.L)) {
-    case 4: return a.L == 4 ? csr_step_lq<4, true>(a, compat, s) : csr_step_lq<4, false>(a, compat, s);
-    case 8: return a.L == 8 ? csr_step_lq<8, true>(a, compat, s) : csr_step_lq<8, false>(a, compat, s);
-    case 12: return csr_step_lq<12, false>(a, compat, s);
-    case 16: return csr_step_lq<16, false>(a, compat, s);
-    case 20: return csr_step_lq<20, false>(a, compat, s);
-    case 24: return csr_step_lq<24, false>(a, compat, s);
-    case 28: return csr_step_lq<28, false>(a, compat, s);
-    default: return csr_step_lq<32, false>(a, compat, s);
+    case 4: return a.L == 4 ? csr_step_lq<4, 4>(a, compat, s) : csr_step_lq<4, 0>(a, compat, s);
+    case 8: return a.L == 8 ? csr_step_lq<8, 8>(a, compat, s) : csr_step_lq<8, 0>(a, compat, s);
+    case 12: return csr_step_lq<12, 0>(a, compat, s);
+    case 16: return csr_step_lq<16, 0>(a, compat, s);
+    case 24: return a.L == 21 ? csr_step_lq<24, 21>(a, compat, s) : csr_step_lq<24, 0>(a, compat, s);
+    default: return csr_step_lq<32, 0>(a, compat, s);
   }
 }
 

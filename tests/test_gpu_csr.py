@@ -32,6 +32,7 @@ def gpu_state(s):
     (2000, 21, 8, True, 1),
     (777, 32, 5, True, 1),
     (4096, 13, 12, False, 1),
+    (1500, 17, 7, True, 1),
 ])
 def test_csr_end_to_end(n, L, deg, weighted, B):
     inst = synth.csr_instance(40 + n + L, n, L, deg, weighted, alpha=0.5, iters=10, batch=B)
@@ -80,9 +81,11 @@ def test_csr_of_a_grid_matches_grid_path():
     assert cases.max_dq(gpu_state(a), gpu_state(c)) <= 2e-6
 
 
-def test_csr_potts_and_free_energy():
-    base = synth.csr_instance(77, 1500, 4, 6, True)
-    inst = synth.Instance(name="csr-potts", graph=synth.CSR, n_labels=4, n_nodes=1500, unary=base.unary,
+@pytest.mark.parametrize("L", [4, 21])
+def test_csr_potts_and_free_energy(L):
+    """One lane per node (L = 4) and two lanes per node (L = 21)."""
+    base = synth.csr_instance(77 + L, 1500, L, 6, True)
+    inst = synth.Instance(name="csr-potts", graph=synth.CSR, n_labels=L, n_nodes=1500, unary=base.unary,
                           compat=synth.COMPAT_POTTS, potts_w=0.75, alpha=0.5, iters=6,
                           row_ptr=base.row_ptr, col=base.col, csr_w=base.csr_w)
     for which in (inst, base):
