@@ -38,8 +38,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_UPDATE = 12          # read log q (4) + read u (4) + write log q' (4)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_step_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_06103_amd", "csrc", f)
-                  for f in ("grid_temporal.h", "grid_lanes.h", "msg_codec.h")]
+# sources of each workload's dominant kernel: a traffic measurement holds
+# only while they are unchanged
+KERNEL_SOURCES = {
+    "grid": ("grid_temporal.h", "grid_lanes.h", "msg_codec.h"),
+    "csr": ("csr_kernels.hip",),
+    "dense": ("dense_kernels.hip",),
+}
 
 WORKLOADS = {
     "grid256_L21_theta": lambda s: s.workload_c2(),
@@ -59,12 +64,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash():
+def source_hash(kind="grid"):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_1511_06103_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def source_kind(inst):
+    return {2: "csr", 3: "dense"}.get(inst.graph, "grid")
 
 
 def make_solver(inst, torch, mf, **extra):
@@ -122,8 +131,8 @@ def step_kernel_name(inst, k):
     dispatch rule: fused steps for k > 1, Theta S on the matrix cores for a
     general Theta with 8 < L <= 32)."""
     L = inst.unary.shape[1]
-    if inst.graph == 3:
-        return "mf::dense_step_kernel"
+    if inst.graph == 3:      # one step is the MFMA kernel and the per-node kernel, back to back
+        return "mf::dense_step_kernel + mf::dense_epilogue_kernel"
     if inst.graph == 2:
         return "mf::csr_step_kernel"
     if k == 1:
@@ -233,7 +242,7 @@ def cpu_baseline(inst, budget_s=12.0):
                       f"({el:.1f} s, 1 thread)"}
 
 
-def load_traffic(workload, k):
+def load_traffic(workload, k, kind):
     """HBM bytes per launch of the dominant kernel measured with rocprofv3
     counters (profiles/), or None when none was taken for this workload and
     launch depth or the kernel sources changed since."""
@@ -244,7 +253,7 @@ def load_traffic(workload, k):
         return None
     for e in t.get("entries", []):
         if (e.get("workload") == workload and e.get("steps_per_launch") == k
-                and e.get("kernel_source_sha256_16") == source_hash()):
+                and e.get("kernel_source_sha256_16") == source_hash(kind)):
             return e.get("hbm_bytes_per_launch")
     return None
 
@@ -325,7 +334,7 @@ def main():
     mean_d, k = time_step_launches(solver, torch, args.launches)
     algo = algorithmic_bytes(inst, k)
     achieved = algo / mean_d / 1e9
-    traffic = load_traffic(inst.name, k)
+    traffic = load_traffic(inst.name, k, source_kind(inst))
     kname = step_kernel_name(inst, k)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
