@@ -130,6 +130,20 @@ def grid_theta_random(seed, height, width=None, n_labels=21, conn=GRID8, batch=1
                     compat=COMPAT_GENERAL, alpha=float(np.float32(alpha)), iters=iters)
 
 
+def grid_repulsive(seed, side, w=2.0, conn=GRID8, alpha=0.5, iters=50, name=None):
+    """Binary grid with a strongly repulsive coupling, Theta = -w (1 1^T - I)
+    (neighbours pay -w for disagreeing), and iid N(0,1) unaries: the kind of
+    model on which undamped parallel updates oscillate (the GRID benchmark's
+    repulsive potentials, Sec. 4).  Draw order: ``standard_normal((2, side, side))``.
+    """
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((2, side, side)).reshape(1, 2, side * side)
+    theta = -float(w) * (np.ones((2, 2)) - np.eye(2))
+    return Instance(name=name or f"repulsive{side}x{side}", graph=conn, n_labels=2, n_nodes=side * side,
+                    height=side, width=side, unary=_f32(u), theta=_f32(theta), compat=COMPAT_GENERAL,
+                    alpha=float(np.float32(alpha)), iters=iters)
+
+
 def workload_c1():
     """32 x 32, 4-connected, L = 2, Potts w = 1, N(0,1) unaries, alpha 0.5, 50 iterations."""
     return grid_potts_normal(1, 32, 2, GRID4, 1.0, 0.5, 50, name="grid32_L2_potts")
