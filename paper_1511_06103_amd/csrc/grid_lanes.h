@@ -398,14 +398,20 @@ __global__ __launch_bounds__(TX * TY * LPN) void step_kernel(StepArgs a, float o
   tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY>(a, one_minus_alpha, b, tx * TX, ty * TY, sm);
 }
 
-// Many independent problems in one launch: slot k owns workgroups
-// [tile_begin[k], tile_begin[k + 1]).
+// Many independent problems in one launch: slot k owns tiles
+// [tile_begin[k], tile_begin[k + 1]).  Tiles are dealt to workgroups XCD by
+// XCD as in step_kernel (adjacent tiles of a problem share an L2), and the
+// slot of a tile is found by binary search over tile_begin.
 template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY>
 __global__ __launch_bounds__(TX * TY * LPN) void step_many_kernel(ManyArgs m) {
   __shared__ Smem<LG, LPN, TX, TY, PREC> sm;
-  const int blk = blockIdx.x;
-  int k = 0;
-  while (k + 1 < m.count && blk >= m.tile_begin[k + 1]) ++k;
+  const int blk = xcd_tile(blockIdx.x, m.tile_begin[m.count]);
+  int k = 0, hi = m.count - 1;            // the last slot with tile_begin <= blk
+  while (k < hi) {
+    const int mid = (k + hi + 1) >> 1;
+    if (m.tile_begin[mid] <= blk) k = mid;
+    else hi = mid - 1;
+  }
   const int t = blk - m.tile_begin[k];
   const int tiles_x = (m.slot[k].W + TX - 1) / TX;
   const int tiles_per_item = tiles_x * ((m.slot[k].H + TY - 1) / TY);
