@@ -100,7 +100,8 @@ def test_dense_small_end_to_end_and_free_energy(small):
         assert abs(F - Fr) <= 1e-9 * max(1.0, abs(Fr)), (t, F, Fr)
 
 
-@pytest.mark.parametrize("n,L,cooc,potts", [(64, 2, False, True), (129, 21, True, True), (517, 7, False, False),
+@pytest.mark.parametrize("n,L,cooc,potts", [(1, 3, True, True), (7, 5, False, False), (64, 2, False, True),
+                                            (129, 21, True, True), (517, 7, False, False),
                                             (1000, 32, True, False), (300, 21, True, False), (776, 21, False, False)])
 def test_dense_variants(n, L, cooc, potts):
     base = synth.dense_instance(5 + n, n, L, pos_high=16.0, iters=6, with_cooc=cooc)
