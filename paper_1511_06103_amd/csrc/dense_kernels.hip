@@ -28,7 +28,7 @@
 // 8 (x / 16) .. + 7 of the chunk.
 //
 // Work split: a workgroup owns a 64-row block and one of KS slices of the
-// j range; its four wavefronts split the slice's 32-column chunks and each
+// j range; its eight wavefronts split the slice's 32-column chunks and each
 // accumulates the whole 64 x 32 (rows x labels, L padded to 32) tile in
 // registers.  Slices write FP32 partial sums.  A second kernel, one
 // workgroup per 64-row block, adds the KS partials in a fixed order and
@@ -150,15 +150,19 @@ __global__ __launch_bounds__(64) void dense_prepare_kernel(DenseStepArgs a) {
 }
 
 // One workgroup: the 64-row block rb against the j slice ks.  Each of the
-// four wavefronts holds the whole 64 x 32 tile (four 16-row MFMA tiles) and
-// takes every fourth 32-column step of the slice, so a Q operand it loads
-// meets four K operands and no two wavefronts load the same Q columns.  The
-// four per-wavefront tiles are added through LDS in wavefront order.
+// kStepWaves wavefronts holds the whole 64 x 32 tile (four 16-row MFMA
+// tiles) and takes every kStepWaves-th 32-column step of the slice, so a Q
+// operand it loads meets four K operands and no two wavefronts load the
+// same Q columns.  The per-wavefront tiles are added through LDS in
+// wavefront order.
 constexpr int kPSt = kLP + 1;    // LDS row stride of the per-wavefront tiles
+constexpr int kStepWaves = 8;    // wavefronts per workgroup of the MFMA kernel (8 measured
+                                 // faster than 4: one load trip per wavefront)
 
 template <int NS>
-__global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
-  __shared__ float part[4 * kRB * kPSt];
+__global__ __launch_bounds__(64 * kStepWaves) void dense_step_kernel(DenseStepArgs a) {
+  constexpr int NW = kStepWaves, NT = 64 * NW;
+  __shared__ float part[NW * kRB * kPSt];
   const int b = blockIdx.y;
   const int rb = blockIdx.x / a.KS, ks = blockIdx.x - (blockIdx.x / a.KS) * a.KS;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -177,16 +181,16 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   // two of the wavefront's steps per trip: all their loads before their MFMAs
   constexpr int U = 2;
   int st = wave;
-  for (; st + 4 * (U - 1) < nst; st += 4 * U) {
+  for (; st + NW * (U - 1) < nst; st += NW * U) {
     bf16x8 av[U][4], bq[U][NS][2];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) av[u][t] = load_k(st + 4 * u, t);
+      for (int t = 0; t < 4; ++t) av[u][t] = load_k(st + NW * u, t);
 #pragma unroll
       for (int p = 0; p < NS; ++p) {
-        bq[u][p][0] = load_q(st + 4 * u, p, 0);
-        bq[u][p][1] = load_q(st + 4 * u, p, 1);
+        bq[u][p][0] = load_q(st + NW * u, p, 0);
+        bq[u][p][1] = load_q(st + NW * u, p, 1);
       }
     }
 #pragma unroll
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
           acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u][t], bq[u][p][1], acc[t][1], 0, 0, 0);
         }
   }
-  for (; st < nst; st += 4) {
+  for (; st < nst; st += NW) {
     bf16x8 av[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) av[t] = load_k(st, t);
@@ -226,9 +230,12 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   __syncthreads();
   float* sp = a.s_part + (((size_t)b * a.KS + ks) * Np + (size_t)rb * kRB) * kLP;
 #pragma unroll
-  for (int r = 0; r < kRB * kLP / 256; ++r) {
-    const int f = tid + 256 * r, o = (f / kLP) * kPSt + (f % kLP);
-    sp[f] = ((part[o] + part[kRB * kPSt + o]) + part[2 * kRB * kPSt + o]) + part[3 * kRB * kPSt + o];
+  for (int r = 0; r < kRB * kLP / NT; ++r) {
+    const int f = tid + NT * r, o = (f / kLP) * kPSt + (f % kLP);
+    float v = part[o];                   // wavefront order
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += part[w * kRB * kPSt + o];
+    sp[f] = v;
   }
 }
 
@@ -487,7 +494,7 @@ hipError_t epilogue_lc(const DenseStepArgs& a, int compat, float om, hipStream_t
 
 template <int NS>
 hipError_t step_ns(const DenseStepArgs& a, int compat, hipStream_t s) {
-  hipLaunchKernelGGL((dense_step_kernel<NS>), dim3(a.NRB * a.KS, a.B), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((dense_step_kernel<NS>), dim3(a.NRB * a.KS, a.B), dim3(64 * kStepWaves), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const float om = (float)(1.0 - (double)a.alpha);
