@@ -241,13 +241,15 @@ __global__ __launch_bounds__(64 * kStepWaves) void dense_step_kernel(DenseStepAr
 
 // The per-node step of one 64-row block: the KS partial sums of S in a fixed
 // order, the message, the step, the next Q planes and the block's column
-// sums of q.  256 threads: lane = node of the block, wavefront w = label
-// group (labels w + 4 j, j < 8).  The partials arrive node-major and are
+// sums of q.  kEpiGroups wavefronts: lane = node of the block, wavefront
+// w = label group (labels w + kEpiGroups j).  The partials arrive node-major and are
 // transposed through LDS (coalesced loads); the terms that mix labels
 // (Theta S, the co-occurrence product, the per-node max and sum) read the
 // node's other labels from LDS.  LC > 0 fixes L at compile time so the
 // label loops unroll; every global load is issued before the first wait.
-constexpr int kEpiThreads = 256;
+constexpr int kEpiGroups = 8;                 // label groups (wavefronts) per 64-node block:
+                                              // 8 measured faster than 4 (shorter per-thread chains)
+constexpr int kEpiThreads = 64 * kEpiGroups;
 constexpr int kSt = kLP + 1;          // LDS row stride of the node x label tiles
 constexpr int kTParts = kEpiThreads / kLP;
 
@@ -261,18 +263,25 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
   __shared__ float Cc[kLP * kLP];      // co-occurrence
   __shared__ float St[kRB * kSt];      // S[node][label]
   __shared__ float Qt[kRB * kSt];      // q[node][label] (co-occurrence)
-  __shared__ float red[4 * kRB];       // per-node partials of the four label groups
+  __shared__ float red[kEpiGroups * kRB];   // per-node partials of the label groups
   __shared__ float Tp[kEpiThreads];    // partial column sums of q at the previous step
   __shared__ float Ts[kLP];
 
   const int i = rb * kRB + lane;
   const bool inside = i < N;
   const size_t base = (size_t)b * L * N + (inside ? i : 0);
-  constexpr int J = kLP / 4;
+  constexpr int NG = kEpiGroups, J = kLP / NG;
+  // per-node total over the label groups, in one fixed order
+  auto group_sum = [&]() {
+    float v = red[lane];
+#pragma unroll
+    for (int g = 1; g < NG; ++g) v += red[g * kRB + lane];
+    return v;
+  };
   float ell[J], un[J], z[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int l = w + 4 * j;
+    const int l = w + NG * j;
     const bool on = inside && l < L;
     ell[j] = on ? a.state_in[base + (size_t)l * N] : 0.f;
     un[j] = on ? a.unary[base + (size_t)l * N] : 0.f;
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
   }
   if (COOC) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) Qt[lane * kSt + w + 4 * j] = (inside && w + 4 * j < L) ? __expf(ell[j]) : 0.f;
+    for (int j = 0; j < J; ++j) Qt[lane * kSt + w + NG * j] = (inside && w + NG * j < L) ? __expf(ell[j]) : 0.f;
   }
   __syncthreads();
   if (COOC && tid < kLP) {
@@ -322,11 +331,11 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
   if (COMPAT == MF_COMPAT_POTTS) {
     float part = 0.f;
 #pragma unroll
-    for (int j = 0; j < J; ++j) part += (w + 4 * j < L) ? St[lane * kSt + w + 4 * j] : 0.f;
+    for (int j = 0; j < J; ++j) part += (w + NG * j < L) ? St[lane * kSt + w + NG * j] : 0.f;
     red[w * kRB + lane] = part;
   }
   __syncthreads();
-  if (COMPAT == MF_COMPAT_POTTS) tot = (red[lane] + red[kRB + lane]) + (red[2 * kRB + lane] + red[3 * kRB + lane]);
+  if (COMPAT == MF_COMPAT_POTTS) tot = group_sum();
   // the node's S and q rows, read once
   float srow[kLP], qrow[kLP];
   if (COMPAT != MF_COMPAT_POTTS) {
@@ -340,7 +349,7 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
   float mx = -INFINITY;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int l = w + 4 * j;
+    const int l = w + NG * j;
     z[j] = -INFINITY;
     if (l < L) {
       float m = un[j];
@@ -370,28 +379,30 @@ __global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepAr
       mx = fmaxf(mx, z[j]);
     }
   }
-  // per-node max and sum over the four label groups, fixed order
+  // per-node max and sum over the label groups, fixed order
   __syncthreads();
   red[w * kRB + lane] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(red[lane], red[kRB + lane]), fmaxf(red[2 * kRB + lane], red[3 * kRB + lane]));
+  mx = red[lane];
+#pragma unroll
+  for (int g = 1; g < NG; ++g) mx = fmaxf(mx, red[g * kRB + lane]);
   __syncthreads();
   float e[J];
   float se = 0.f;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    e[j] = (w + 4 * j < L) ? __expf(z[j] - mx) : 0.f;
+    e[j] = (w + NG * j < L) ? __expf(z[j] - mx) : 0.f;
     se += e[j];
   }
   red[w * kRB + lane] = se;
   __syncthreads();
-  se = (red[lane] + red[kRB + lane]) + (red[2 * kRB + lane] + red[3 * kRB + lane]);
+  se = group_sum();
   const float lse = mx + __logf(se);
   const float inv = 1.0f / se;
   unsigned short* planes = a.q_out + (size_t)b * NS * kLP * Np;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int l = w + 4 * j;
+    const int l = w + NG * j;
     const float q = inside ? e[j] * inv : 0.f;
     if (inside && l < L) a.state_out[base + (size_t)l * N] = z[j] - lse;
     store_planes<NS>(planes, l, i, q);
