@@ -17,10 +17,27 @@
 // over tiles, and is deterministic.
 #include <hip/hip_runtime.h>
 
+#include "grid_lanes.h"
 #include "mf_internal.h"
 
 namespace mf {
 namespace {
+
+// Tile of this workgroup, dealt XCD by XCD as in the forward step kernel so
+// that neighbouring tiles (which read each other's halo) share an L2.
+struct AdjTile {
+  int t, b, x0, y0;
+};
+__device__ inline AdjTile adj_tile(const AdjointArgs& a) {
+  const int tx = (a.W + kTileX - 1) / kTileX, ty = (a.H + kTileY - 1) / kTileY;
+  AdjTile r;
+  r.t = lanes::xcd_tile(blockIdx.x, tx * ty * a.B);
+  r.b = r.t / (tx * ty);
+  const int q = r.t - r.b * (tx * ty);
+  r.y0 = (q / tx) * kTileY;
+  r.x0 = (q - (q / tx) * tx) * kTileX;
+  return r;
+}
 
 constexpr int AX = kTileX + 2;
 constexpr int AY = kTileY + 2;
@@ -72,8 +89,8 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
   __shared__ float red[NB == 1 ? 4 * 256 : 1];
   const int L = EXACT ? LP : a.L;
   const int N = a.N, H = a.H, W = a.W;
-  const int b = blockIdx.z;
-  const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+  const AdjTile tile = adj_tile(a);
+  const int b = tile.b, x0 = tile.x0, y0 = tile.y0;
   const size_t base = (size_t)b * L * N;
   const int tid = threadIdx.x;
   const int tx = tid % kTileX, ty = tid / kTileX;
@@ -171,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
       const float bv = kc < LP ? Ss[kc * RS + j] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
     }
-    const size_t part = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const size_t part = (size_t)tile.t;
     double* out = a.theta_tile + part * L * L;
     if constexpr (WPB == 1) {
 #pragma unroll
@@ -201,8 +218,8 @@ __global__ __launch_bounds__(kThreads) void adj_b_kernel(AdjointArgs a) {
   __shared__ float sb[LP * AN];
   const int L = EXACT ? LP : a.L;
   const int N = a.N, H = a.H, W = a.W;
-  const int b = blockIdx.z;
-  const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+  const AdjTile tile = adj_tile(a);
+  const int b = tile.b, x0 = tile.x0, y0 = tile.y0;
   const size_t base = (size_t)b * L * N;
   const int tid = threadIdx.x;
   const int tx = tid % kTileX, ty = tid / kTileX;
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(256) void f64_to_f32(const double* __restrict__ s, 
 
 template <int LP, bool EXACT>
 hipError_t adj_lp(const AdjointArgs& a, int conn, int compat, hipStream_t s) {
-  dim3 grid((a.W + kTileX - 1) / kTileX, (a.H + kTileY - 1) / kTileY, a.B);
+  const dim3 grid((unsigned)adjoint_theta_parts(a.B, a.H, a.W));
   if (conn == 4) {
     if (compat == MF_COMPAT_POTTS) hipLaunchKernelGGL((adj_a_kernel<LP, EXACT, 4, MF_COMPAT_POTTS>), grid, dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL((adj_a_kernel<LP, EXACT, 4, MF_COMPAT_GENERAL>), grid, dim3(kThreads), 0, s, a);
