@@ -6,16 +6,20 @@
 namespace mf {
 namespace {
 
+// Tiles dealt to workgroups XCD by XCD, as in the fixed-step kernel.
 template <int LG, int LC, int CONN, int COMPAT, int RULE>
 __global__ __launch_bounds__(64 * 4) void rule_step_kernel(StepArgs a, RuleArgs r) {
   __shared__ lanes::Smem<LG, 1, 64, 4, P_F32> sm;
-  lanes::tile_step<LG, 1, LC, CONN, COMPAT, P_F32, 64, 4, RULE>(a, 1.0f - a.alpha, blockIdx.z, blockIdx.x * 64,
-                                                                 blockIdx.y * 4, sm, &r);
+  const int tiles_x = (a.W + 63) / 64, per_item = tiles_x * ((a.H + 3) / 4);
+  const int t = lanes::xcd_tile(blockIdx.x, per_item * a.B);
+  const int b = t / per_item, q = t - b * per_item;
+  const int ty = q / tiles_x, tx = q - ty * tiles_x;
+  lanes::tile_step<LG, 1, LC, CONN, COMPAT, P_F32, 64, 4, RULE>(a, 1.0f - a.alpha, b, tx * 64, ty * 4, sm, &r);
 }
 
 template <int LG, int LC, int RULE>
 hipError_t go(const StepArgs& a, const RuleArgs& r, int conn, int compat, hipStream_t s) {
-  const dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, a.B), block(64 * 4);
+  const dim3 grid(((a.W + 63) / 64) * ((a.H + 3) / 4) * a.B), block(64 * 4);
   if (conn == 4) {
     if (compat == MF_COMPAT_POTTS)
       hipLaunchKernelGGL((rule_step_kernel<LG, LC, 4, MF_COMPAT_POTTS, RULE>), grid, block, 0, s, a, r);

@@ -16,6 +16,7 @@
 // every sum FP64.
 #include <hip/hip_runtime.h>
 
+#include "grid_lanes.h"
 #include "mf_internal.h"
 
 namespace mf {
@@ -151,7 +152,11 @@ __global__ __launch_bounds__(kGT * kGT) void lip_hvp_grid_kernel(LipArgs a) {
   __shared__ float tile[LC * kGH * kGH];
   const unsigned N = (unsigned)a.N;
   const int L = a.L, H = a.H, W = a.W;
-  const int x0 = blockIdx.x * kGT - 1, y0 = blockIdx.y * kGT - 1;
+  // tiles dealt XCD by XCD (neighbouring tiles share an L2); the partial
+  // sums are indexed by the tile, so their order is fixed
+  const int tiles_x = (W + kGT - 1) / kGT;
+  const int tid_t = lanes::xcd_tile(blockIdx.x, tiles_x * ((H + kGT - 1) / kGT));
+  const int x0 = (tid_t - (tid_t / tiles_x) * tiles_x) * kGT - 1, y0 = (tid_t / tiles_x) * kGT - 1;
   stage_theta<LC>(a, th, kGT * kGT);
   for (int f = threadIdx.x; f < LC * kGH * kGH; f += kGT * kGT) {
     const int l = f / (kGH * kGH), c = f - l * (kGH * kGH);
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(kGT * kGT) void lip_hvp_grid_kernel(LipArgs a) {
     }
     hvp_finish<LC>(a, th, S, vo, scale, shift, n, x);
   }
-  block_sum_store<3>(x, red, a.part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * a.np);
+  block_sum_store<3>(x, red, a.part + (size_t)tid_t * a.np);
 }
 
 // CSR: one thread per node gathering its row.
@@ -412,7 +417,7 @@ hipError_t launch_lip_hvp(const LipArgs& a, hipStream_t s) {
       else if (L == 21) hipLaunchKernelGGL(lip_hvp_csr_kernel<21>, grid, block, 0, s, a);
       else hipLaunchKernelGGL(lip_hvp_csr_kernel<32>, grid, block, 0, s, a);
     } else {
-      const dim3 grid((unsigned)((a.W + kGT - 1) / kGT), (unsigned)((a.H + kGT - 1) / kGT)), block(kGT * kGT);
+      const dim3 grid((unsigned)(((a.W + kGT - 1) / kGT) * ((a.H + kGT - 1) / kGT))), block(kGT * kGT);
       if (L <= 2) hipLaunchKernelGGL(lip_hvp_grid_kernel<2>, grid, block, 0, s, a);
       else if (L <= 4) hipLaunchKernelGGL(lip_hvp_grid_kernel<4>, grid, block, 0, s, a);
       else if (L <= 8) hipLaunchKernelGGL(lip_hvp_grid_kernel<8>, grid, block, 0, s, a);
