@@ -18,6 +18,13 @@ Discrete Random Fields"):
 * ``alpha = eta = 1 / (1 + d)`` (Eq. 16, Sec. 3.2).
 
 All arrays are label-major, ``[L, N]``, float64.
+
+Pins (tests/test_oracle_pins.py): every function here is checked against
+closed forms, brute force, independent library routines or special cases
+that reduce it to another pinned function, with one exception: the
+second-moment average of ``adam_solve`` for gamma2 < 1 (a reading of a
+garbled passage, Sec. 3.5) is checked only through fixed-point
+preservation and normalisation -- parity unpinned for that part.
 """
 from __future__ import annotations
 

@@ -541,6 +541,24 @@ def test_adam_and_momentum_preserve_fixed_points():
         assert np.abs(np.exp(e).sum(0) - 1).max() < 1e-12
 
 
+def test_adam_with_frozen_second_moment_is_a_fixed_step():
+    """With gamma1 = 0 the direction is the current message and with
+    gamma2 = 1 the second moment stays at v0, so d^t = sqrt(v0) d + eps - 1
+    at every node-label: ADAM is then the fixed proximal step (Eq. 15-16)
+    with eta = 1 / (sqrt(v0) d + eps), which the KKT and closed-form pins
+    above fix.  Each case checks one part of the ADAM reading: the momentum
+    placement, the second-moment placement, the square root, eps and the
+    -1 of Eq. 23."""
+    inst = synth.grid_theta_random(9, 6, 7, 4, synth.GRID8)
+    model = _model_from(inst)
+    d = 3.0
+    for v0, eps, eta in ((1.0, 0.0, 1.0 / d), (4.0, 0.0, 1.0 / (2.0 * d)), (1.0, 0.5, 1.0 / (d + 0.5))):
+        a = O.adam_solve(model, d, 6, gamma1=0.0, gamma2=1.0, eps=eps, v0=v0)
+        b = O.solve(model, eta, 6)
+        for x, y in zip(a, b):
+            np.testing.assert_allclose(x, y, atol=1e-13)
+
+
 def test_paper_constants_fixture():
     c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     import inspect
