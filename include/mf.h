@@ -30,8 +30,9 @@
  *   memory: scratch space is the caller's workspace buffer, sized by
  *   mf_workspace_size.  The library owns only the host-side handle.
  * - Streams.  Work is enqueued asynchronously on the caller's hipStream_t
- *   (desc.stream, NULL = the default stream).  Only mf_free_energy and
- *   mf_check synchronise that stream.
+ *   (desc.stream, NULL = the default stream).  Only mf_free_energy,
+ *   mf_check and mf_lipschitz (whose results are host values) synchronise
+ *   that stream.
  * - Errors.  Every entry point returns an mf_status; nothing throws or
  *   aborts across the ABI.  Arguments are validated on the host before any
  *   launch.  mf_last_error gives a message for the last failure.
