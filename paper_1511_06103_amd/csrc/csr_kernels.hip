@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "mf_internal.h"
+#include "msg_codec.h"
 
 namespace mf {
 namespace {
@@ -44,10 +45,46 @@ __global__ __launch_bounds__(kCsrThreads) void csr_check_kernel(const int* __res
   if (bad) atomicOr(flags, 2);
 }
 
+// Four consecutive labels of a node-major q row: one 16-byte load in FP32,
+// one 8-byte load of 16-bit values in the BF16 / FP16 message modes (the
+// operand rounding of the neighbour aggregation, as on grids).
+template <int PREC>
+struct Q4 {
+  using M = MsgT<PREC>;
+  using C = typename std::conditional<PREC == P_F32, float4, uint2>::type;
+  __device__ static unsigned short bits(typename M::T h) {
+    if constexpr (PREC == P_F16) return __builtin_bit_cast(unsigned short, h);
+    else return (unsigned short)h;
+  }
+  __device__ static float dec16(unsigned int b) {
+    if constexpr (PREC == P_F16) return M::dec(__builtin_bit_cast(_Float16, (unsigned short)b));
+    else return M::dec((unsigned short)b);
+  }
+  __device__ static void dec(const C& c, float (&v)[4]) {
+    if constexpr (PREC == P_F32) {
+      v[0] = c.x; v[1] = c.y; v[2] = c.z; v[3] = c.w;
+    } else {
+      v[0] = dec16(c.x & 0xFFFFu); v[1] = dec16(c.x >> 16);
+      v[2] = dec16(c.y & 0xFFFFu); v[3] = dec16(c.y >> 16);
+    }
+  }
+  __device__ static C enc(float a, float b, float c, float d) {
+    if constexpr (PREC == P_F32) {
+      return make_float4(a, b, c, d);
+    } else {
+      C r;
+      r.x = (unsigned int)bits(M::enc(a)) | ((unsigned int)bits(M::enc(b)) << 16);
+      r.y = (unsigned int)bits(M::enc(c)) | ((unsigned int)bits(M::enc(d)) << 16);
+      return r;
+    }
+  }
+};
+
 // Node-major q from the label-major log q (after initialisation).
-template <int LQ>
+template <int LQ, int PREC>
 __global__ __launch_bounds__(kCsrThreads) void csr_q_from_state_kernel(const float* __restrict__ state,
-                                                                       float* __restrict__ qn, int L, int N) {
+                                                                       void* __restrict__ qn, int L, int N) {
+  using Q = Q4<PREC>;
   const int i = blockIdx.x * kCsrThreads + threadIdx.x;
   const int b = blockIdx.y;
   if (i >= N) return;
@@ -55,9 +92,9 @@ __global__ __launch_bounds__(kCsrThreads) void csr_q_from_state_kernel(const flo
   float v[LQ];
 #pragma unroll
   for (int l = 0; l < LQ; ++l) v[l] = (l < L) ? expf(s[(size_t)l * N]) : 0.f;
-  float4* dst = reinterpret_cast<float4*>(qn + ((size_t)b * N + i) * LQ);
+  typename Q::C* dst = reinterpret_cast<typename Q::C*>(qn) + ((size_t)b * N + i) * (LQ / 4);
 #pragma unroll
-  for (int k = 0; k < LQ / 4; ++k) dst[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  for (int k = 0; k < LQ / 4; ++k) dst[k] = Q::enc(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
 }
 
 // Partner lane of a node (P = 2): lanes 2n and 2n + 1 swap a value (DPP
@@ -74,10 +111,12 @@ __device__ inline float partner(float v) {
 // the dependent row_ptr -> col -> q loads.  LC > 0: L == LC at compile
 // time.  Theta is staged in LDS zero-padded to LQ x LQ, so the message needs
 // no per-label test for any L; padded labels carry z = -inf (q = 0).
-template <int LQ, int LC, int COMPAT, int P>
+template <int LQ, int LC, int COMPAT, int P, int PREC>
 __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, float one_minus_alpha) {
+  using Q = Q4<PREC>;
+  using C = typename Q::C;
   constexpr int LH = LQ / P;
-  static_assert(LH % 4 == 0, "each lane gathers whole float4 slices");
+  static_assert(LH % 4 == 0, "each lane gathers whole four-label slices");
   __shared__ float Th[COMPAT == MF_COMPAT_GENERAL ? LQ * LQ : 1];
   const int L = LC > 0 ? LC : a.L;
   const int N = a.N;
@@ -110,7 +149,7 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
   float S[LH];
 #pragma unroll
   for (int u = 0; u < LH; ++u) S[u] = 0.f;
-  const float4* __restrict__ qb = reinterpret_cast<const float4*>(a.q_in + (size_t)b * N * LQ) + h * (LH / 4);
+  const C* __restrict__ qb = reinterpret_cast<const C*>(a.q_in) + (size_t)b * N * (LQ / 4) + h * (LH / 4);
   // Clamp the row to [0, nnz) and skip out-of-range columns: a malformed CSR
   // (reported through the flags by csr_check_kernel) never reads out of bounds.
   long long e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
@@ -133,10 +172,10 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
       j[u] = ok ? jj : 0;
       w[u] = ok ? ww : 0.f;
     }
-    float4 v[EB][LH / 4];
+    C v[EB][LH / 4];
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
-      const float4* qj = qb + (size_t)j[u] * (LQ / 4);
+      const C* qj = qb + (size_t)j[u] * (LQ / 4);
 #pragma unroll
       for (int k = 0; k < LH / 4; ++k) v[u][k] = qj[k];
     }
@@ -144,10 +183,10 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
     for (int u = 0; u < EB; ++u) {
 #pragma unroll
       for (int k = 0; k < LH / 4; ++k) {
-        S[4 * k] = fmaf(w[u], v[u][k].x, S[4 * k]);
-        S[4 * k + 1] = fmaf(w[u], v[u][k].y, S[4 * k + 1]);
-        S[4 * k + 2] = fmaf(w[u], v[u][k].z, S[4 * k + 2]);
-        S[4 * k + 3] = fmaf(w[u], v[u][k].w, S[4 * k + 3]);
+        float f[4];
+        Q::dec(v[u][k], f);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) S[4 * k + c] = fmaf(w[u], f[c], S[4 * k + c]);
       }
     }
   }
@@ -203,10 +242,10 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
 #pragma unroll
   for (int u = 0; u < LH; ++u)
     if (l0 + u < L) out[(size_t)(l0 + u) * N] = z[u] - lse;
-  float4* qo = reinterpret_cast<float4*>(a.q_out + ((size_t)b * N + i) * LQ) + h * (LH / 4);
+  C* qo = reinterpret_cast<C*>(a.q_out) + ((size_t)b * N + i) * (LQ / 4) + h * (LH / 4);
 #pragma unroll
   for (int k = 0; k < LH / 4; ++k)
-    qo[k] = make_float4(e[4 * k] * inv, e[4 * k + 1] * inv, e[4 * k + 2] * inv, e[4 * k + 3] * inv);
+    qo[k] = Q::enc(e[4 * k] * inv, e[4 * k + 1] * inv, e[4 * k + 2] * inv, e[4 * k + 3] * inv);
 }
 
 __device__ inline double wave_sum_d(double v) {
@@ -274,22 +313,36 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
   if (threadIdx.x == 0) a.partials[(size_t)b * a.n_blocks + blockIdx.x] = t;
 }
 
-template <int LQ, int LC>
-hipError_t csr_step_lq(const CsrStepArgs& a, int compat, hipStream_t s) {
+template <int LQ, int LC, int PREC>
+hipError_t csr_step_prec(const CsrStepArgs& a, int compat, hipStream_t s) {
   constexpr int P = LQ >= 16 ? 2 : 1;
   dim3 grid((unsigned)(((size_t)a.N * P + kCsrThreads - 1) / kCsrThreads), a.B);
   const float om = (float)(1.0 - (double)a.alpha);
   if (compat == MF_COMPAT_POTTS)
-    hipLaunchKernelGGL((csr_step_kernel<LQ, LC, MF_COMPAT_POTTS, P>), grid, dim3(kCsrThreads), 0, s, a, om);
+    hipLaunchKernelGGL((csr_step_kernel<LQ, LC, MF_COMPAT_POTTS, P, PREC>), grid, dim3(kCsrThreads), 0, s, a, om);
   else
-    hipLaunchKernelGGL((csr_step_kernel<LQ, LC, MF_COMPAT_GENERAL, P>), grid, dim3(kCsrThreads), 0, s, a, om);
+    hipLaunchKernelGGL((csr_step_kernel<LQ, LC, MF_COMPAT_GENERAL, P, PREC>), grid, dim3(kCsrThreads), 0, s, a, om);
   return hipGetLastError();
 }
 
+template <int LQ, int LC>
+hipError_t csr_step_lq(const CsrStepArgs& a, int compat, int prec, hipStream_t s) {
+  switch (prec) {
+    case MF_P_F32: return csr_step_prec<LQ, LC, P_F32>(a, compat, s);
+    case MF_P_BF16MSG: return csr_step_prec<LQ, LC, P_BF16>(a, compat, s);
+    default: return csr_step_prec<LQ, LC, P_F16>(a, compat, s);
+  }
+}
+
 template <int LQ>
-hipError_t csr_q_lq(const float* state, float* qn, int B, int L, int N, hipStream_t s) {
+hipError_t csr_q_lq(const float* state, void* qn, int B, int L, int N, int prec, hipStream_t s) {
   dim3 grid((N + kCsrThreads - 1) / kCsrThreads, B);
-  hipLaunchKernelGGL((csr_q_from_state_kernel<LQ>), grid, dim3(kCsrThreads), 0, s, state, qn, L, N);
+  if (prec == MF_P_F32)
+    hipLaunchKernelGGL((csr_q_from_state_kernel<LQ, P_F32>), grid, dim3(kCsrThreads), 0, s, state, qn, L, N);
+  else if (prec == MF_P_BF16MSG)
+    hipLaunchKernelGGL((csr_q_from_state_kernel<LQ, P_BF16>), grid, dim3(kCsrThreads), 0, s, state, qn, L, N);
+  else
+    hipLaunchKernelGGL((csr_q_from_state_kernel<LQ, P_F16>), grid, dim3(kCsrThreads), 0, s, state, qn, L, N);
   return hipGetLastError();
 }
 
@@ -305,25 +358,29 @@ hipError_t launch_csr_check(const int* row_ptr, const int* col, int N, long long
   return hipGetLastError();
 }
 
-hipError_t launch_csr_q_from_state(const float* state, float* qn, int B, int L, int N, hipStream_t s) {
+int csr_q_bytes(int precision) { return precision == MF_P_F32 ? 4 : 2; }
+
+hipError_t launch_csr_q_from_state(const float* state, void* qn, int B, int L, int N, int precision,
+                                   hipStream_t s) {
   switch (csr_label_stride(L)) {
-    case 4: return csr_q_lq<4>(state, qn, B, L, N, s);
-    case 8: return csr_q_lq<8>(state, qn, B, L, N, s);
-    case 12: return csr_q_lq<12>(state, qn, B, L, N, s);
-    case 16: return csr_q_lq<16>(state, qn, B, L, N, s);
-    case 24: return csr_q_lq<24>(state, qn, B, L, N, s);
-    default: return csr_q_lq<32>(state, qn, B, L, N, s);
+    case 4: return csr_q_lq<4>(state, qn, B, L, N, precision, s);
+    case 8: return csr_q_lq<8>(state, qn, B, L, N, precision, s);
+    case 12: return csr_q_lq<12>(state, qn, B, L, N, precision, s);
+    case 16: return csr_q_lq<16>(state, qn, B, L, N, precision, s);
+    case 24: return csr_q_lq<24>(state, qn, B, L, N, precision, s);
+    default: return csr_q_lq<32>(state, qn, B, L, N, precision, s);
   }
 }
 
-hipError_t launch_csr_step(const CsrStepArgs& a, int compat, hipStream_t s) {
+hipError_t launch_csr_step(const CsrStepArgs& a, int compat, int precision, hipStream_t s) {
   switch (csr_label_stride(a.L)) {
-    case 4: return a.L == 4 ? csr_step_lq<4, 4>(a, compat, s) : csr_step_lq<4, 0>(a, compat, s);
-    case 8: return a.L == 8 ? csr_step_lq<8, 8>(a, compat, s) : csr_step_lq<8, 0>(a, compat, s);
-    case 12: return csr_step_lq<12, 0>(a, compat, s);
-    case 16: return csr_step_lq<16, 0>(a, compat, s);
-    case 24: return a.L == 21 ? csr_step_lq<24, 21>(a, compat, s) : csr_step_lq<24, 0>(a, compat, s);
-    default: return csr_step_lq<32, 0>(a, compat, s);
+    case 4: return a.L == 4 ? csr_step_lq<4, 4>(a, compat, precision, s) : csr_step_lq<4, 0>(a, compat, precision, s);
+    case 8: return a.L == 8 ? csr_step_lq<8, 8>(a, compat, precision, s) : csr_step_lq<8, 0>(a, compat, precision, s);
+    case 12: return csr_step_lq<12, 0>(a, compat, precision, s);
+    case 16: return csr_step_lq<16, 0>(a, compat, precision, s);
+    case 24:
+      return a.L == 21 ? csr_step_lq<24, 21>(a, compat, precision, s) : csr_step_lq<24, 0>(a, compat, precision, s);
+    default: return csr_step_lq<32, 0>(a, compat, precision, s);
   }
 }
 

@@ -50,7 +50,7 @@ mf::WorkspaceLayout layout_for(const mf_desc& d) {
   off += align256(sizeof(double) * (size_t)d.batch);
   if (d.graph == MF_CSR) {
     w.csr_q = off;
-    off += align256(sizeof(float) * 2 * (size_t)d.batch * (size_t)d.n_nodes *
+    off += align256((size_t)mf::csr_q_bytes(d.precision) * 2 * (size_t)d.batch * (size_t)d.n_nodes *
                     (size_t)mf::csr_label_stride(d.n_labels));
   }
   if (d.graph == MF_DENSE) {
@@ -202,9 +202,10 @@ mf::DenseStepArgs dense_args(const mf_handle* h, int from) {
   return a;
 }
 
-float* csr_q(const mf_handle* h, int which) {
-  const size_t elems = (size_t)h->d.batch * h->d.n_nodes * mf::csr_label_stride(h->d.n_labels);
-  return (float*)((char*)h->d.workspace + h->ws.csr_q) + (size_t)which * elems;
+void* csr_q(const mf_handle* h, int which) {
+  const size_t bytes = (size_t)h->d.batch * h->d.n_nodes * mf::csr_label_stride(h->d.n_labels) *
+                       (size_t)mf::csr_q_bytes(h->d.precision);
+  return (char*)h->d.workspace + h->ws.csr_q + (size_t)which * bytes;
 }
 
 mf::StepArgs grid_args(const mf_handle* h, int from) {
@@ -259,7 +260,8 @@ mf_status enqueue_init(mf_handle* h, bool clear_flags) {
   e = mf::launch_init(d.unary, buf(h, 0), d.batch, d.n_labels, d.n_nodes, d.init, flags_ptr(h), h->stream);
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("init launch: ") + hipGetErrorString(e));
   if (d.graph == MF_CSR) {
-    e = mf::launch_csr_q_from_state(buf(h, 0), csr_q(h, 0), d.batch, d.n_labels, d.n_nodes, h->stream);
+    e = mf::launch_csr_q_from_state(buf(h, 0), csr_q(h, 0), d.batch, d.n_labels, d.n_nodes, d.precision,
+                                    h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("CSR q launch: ") + hipGetErrorString(e));
   }
   if (d.graph == MF_DENSE) {
@@ -321,7 +323,7 @@ mf_status enqueue_csr_steps(mf_handle* h, int n) {
     a.N = d.n_nodes;
     a.alpha = (float)d.alpha;
     a.potts_w = d.potts_w;
-    hipError_t e = mf::launch_csr_step(a, d.compat, h->stream);
+    hipError_t e = mf::launch_csr_step(a, d.compat, d.precision, h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("CSR step launch: ") + hipGetErrorString(e));
     h->cur ^= 1;
     h->iter += 1;

@@ -49,8 +49,9 @@ struct CsrStepArgs {
   const float* unary;      // [B][L][N]
   const float* state_in;   // [B][L][N]
   float* state_out;        // [B][L][N]
-  const float* q_in;       // [B][N][LQ] node-major q of state_in
-  float* q_out;            // [B][N][LQ] node-major q of state_out
+  const void* q_in;        // [B][N][LQ] node-major q of state_in: FP32, or BF16 / FP16
+                           // in the message-precision modes
+  void* q_out;             // [B][N][LQ] node-major q of state_out
   const int* row_ptr;      // [N + 1]
   const int* col;          // [nnz]
   const float* w;          // [nnz] or nullptr
@@ -159,7 +160,7 @@ struct WorkspaceLayout {
   size_t flags = 0;        // int32[64]: [0] bit 0 non-finite input, bit 1 malformed CSR
   size_t partials = 0;     // double[B][n_blocks]
   size_t f_out = 0;        // double[B]
-  size_t csr_q = 0;        // float[2][B][N][LQ] (CSR only)
+  size_t csr_q = 0;        // [2][B][N][LQ] q, FP32 or 16-bit per message mode (CSR only)
   size_t dq = 0;           // uint16[2][B][NS * 32 * Np] q planes (dense only)
   size_t dk = 0;           // uint16[Np * Np] K in MFMA operand order
   size_t ds = 0;           // float[B][KS][Np][32] partial S
@@ -203,8 +204,11 @@ hipError_t launch_reduce_partials(const double* partials, int n_blocks, int B, d
 int csr_label_stride(int L);
 hipError_t launch_csr_check(const int* row_ptr, const int* col, int N, long long nnz, int* flags,
                             hipStream_t s);
-hipError_t launch_csr_q_from_state(const float* state, float* qn, int B, int L, int N, hipStream_t s);
-hipError_t launch_csr_step(const CsrStepArgs& a, int compat, hipStream_t s);
+// Bytes per element of the node-major q copy: 4 (FP32) or 2 (BF16 / FP16 messages).
+int csr_q_bytes(int precision);
+hipError_t launch_csr_q_from_state(const float* state, void* qn, int B, int L, int N, int precision,
+                                   hipStream_t s);
+hipError_t launch_csr_step(const CsrStepArgs& a, int compat, int precision, hipStream_t s);
 hipError_t launch_csr_free_energy(const CsrFreeEnergyArgs& a, int compat, hipStream_t s);
 
 size_t adjoint_theta_parts(int B, int H, int W);

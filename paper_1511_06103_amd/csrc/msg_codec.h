@@ -1,5 +1,6 @@
-// Storage codecs of the neighbour-message operand q in LDS, one per
-// precision mode: FP32, BF16 (round to nearest even) or FP16.
+// Storage codecs of the neighbour-message operand q (in LDS on grids, the
+// node-major copy in HBM on general graphs), one per precision mode: FP32,
+// BF16 (round to nearest even) or FP16.
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -62,6 +62,61 @@ def test_csr_one_step_from_identical_state():
     assert cases.max_dq(gpu_state(s)[0], ref) <= 1e-6
 
 
+def mean_dq(a, b):
+    return float(np.abs(np.exp(a) - np.exp(b)).mean())
+
+
+def rounding(precision):
+    return O.round_to_bf16 if precision == "bf16" else O.round_to_f16
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16", 2e-3), ("f16", 2e-4)])
+@pytest.mark.parametrize("L", [4, 13, 21])
+def test_csr_message_precision_one_step(L, precision, tol):
+    """The BF16 / FP16 message modes round q to 16 bits where it is gathered
+    (one lane per node at L = 4, two at L = 13 and 21).  One step from an
+    identical state is within the operand-rounding bound of the FP64 step, as
+    on grids, and sits on the oracle step with q rounded the same way: the
+    mean |dq| to it is under a tenth of the rounding's own effect (an FP32
+    gather would sit a whole rounding effect away; the rest is roundings that
+    FP32 ulps in exp(log q) tip the other way)."""
+    inst = synth.csr_instance(90 + L, 3000, L, 8, True)
+    model = cases.oracle_model(inst)
+    start = O.solve(model, 0.5, 5)[-1].astype(np.float32)
+    B, _, N = inst.unary.shape
+    st = torch.empty((2, B, L, N), dtype=torch.float32, device="cuda:0")
+    st[0].copy_(torch.from_numpy(start[None]))
+    s = cases.gpu_solver(inst, init="state", state=st, precision=precision)
+    s.step(1)
+    g = gpu_state(s)[0]
+    ref = O.prox_step(start.astype(np.float64), model, 0.5)
+    emul = O.prox_step(start.astype(np.float64), model, 0.5, operand=rounding(precision))
+    err = cases.max_dq(g, ref)
+    assert err <= tol, (precision, err)
+    assert mean_dq(g, emul) <= 0.1 * mean_dq(emul, ref), (mean_dq(g, emul), mean_dq(emul, ref))
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
+def test_csr_message_precision_end_to_end(precision):
+    """Ten steps with q rounded where it is gathered, batch of two.  Against
+    the oracle run with the same operand rounding the mean |dq| stays under
+    half the rounding's own effect (FP32 noise in the state tips some
+    roundings, about a quarter of it for FP16 in a CPU model of that noise);
+    against the exact FP64 run the max |dq| is within 1.25x that of the
+    rounded oracle run."""
+    inst = synth.csr_instance(95, 2000, 21, 8, True, alpha=0.5, iters=10, batch=2)
+    s = cases.gpu_solver(inst, precision=precision)
+    s.step(10)
+    g = gpu_state(s)
+    for b in range(2):
+        model = cases.oracle_model(inst, b)
+        emul = O.solve(model, 0.5, 10, operand=rounding(precision))[-1]
+        exact = O.solve(model, 0.5, 10)[-1]
+        floor = cases.max_dq(emul, exact)
+        assert mean_dq(g[b], emul) <= 0.5 * mean_dq(emul, exact), b
+        assert cases.max_dq(g[b], exact) <= 1.25 * floor, (b, cases.max_dq(g[b], exact), floor)
+
+
 def test_csr_of_a_grid_matches_grid_path():
     ginst = synth.grid_theta_random(8, 40, 33, 5, synth.GRID8, iters=8)
     edges = O.grid_edges(40, 33, 8)
