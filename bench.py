@@ -27,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -42,7 +43,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_step_traffic.json")
 # only while they are unchanged
 KERNEL_SOURCES = {
     "grid": ("grid_temporal.h", "grid_lanes.h", "msg_codec.h"),
-    "csr": ("csr_kernels.hip",),
+    "csr": ("csr_kernels.hip", "msg_codec.h"),
     "dense": ("dense_kernels.hip",),
 }
 
@@ -96,13 +97,14 @@ def make_solver(inst, torch, mf, **extra):
     return mf.MeanField(u, "dense", dense_K=K, cooc=cooc, **kw)
 
 
-def algorithmic_bytes(inst, k):
+def algorithmic_bytes(inst, k, precision="f32"):
     """Unique bytes one launch of the dominant kernel must move, k steps."""
     B, L, N = inst.unary.shape
     if inst.graph == 3:      # dense: the BF16 K stream (2 N^2 B) and the state (12 B per node-label)
         return k * B * (2 * N * N + BYTES_PER_UPDATE * N * L)
     if inst.graph == 2:      # CSR: log q, u, log q' and the node-major q copy written and gathered
-        return k * B * N * L * (BYTES_PER_UPDATE + 8)
+        qb = 4 if precision == "f32" else 2
+        return k * B * N * L * (BYTES_PER_UPDATE + 2 * qb)
     return BYTES_PER_UPDATE * B * N * L * k
 
 
@@ -210,9 +212,22 @@ def bench_adjoint(args, inst, torch, mf):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(inst, budget_s=12.0):
-    """The FP64 oracle, untuned, timed on this host on a bounded sample."""
-    from threadpoolctl import threadpool_limits
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(inst, budget_s=8.0):
+    """The FP64 oracle, untuned, timed on this host on a bounded sample: once
+    with one thread, once with the BLAS pool at its default size (only the
+    Theta S products use it; the rest of the oracle is single-threaded NumPy)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import oracle as O
     b = 0
@@ -227,7 +242,9 @@ def cpu_baseline(inst, budget_s=12.0):
         K = O.round_to_bf16(O.gaussian_kernel(inst.features))
         cooc = None if inst.cooc is None else inst.cooc.astype(np.float64)
         model = O.dense_model(u, K, theta=th, potts_w=pw, cooc=cooc)
-    with threadpool_limits(1):
+    L, N = model.unary.shape
+
+    def timed():
         ell = O.init_state(model.unary)
         O.prox_step(ell, model, inst.alpha)     # build caches outside the timing
         steps = 0
@@ -236,16 +253,24 @@ def cpu_baseline(inst, budget_s=12.0):
             ell = O.prox_step(ell, model, inst.alpha)
             steps += 1
         el = time.perf_counter() - t0
-    L, N = model.unary.shape
+        return steps, el
+
+    with threadpool_limits(1):
+        steps, el = timed()
+    blas_threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    steps_all, el_all = timed()
     return {"value": steps * N * L / el, "unit": "node-label updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} FP64 proximal steps of one {inst.name} problem (N={N}, L={L}) "
-                      f"({el:.1f} s, 1 thread)"}
+                      f"({el:.1f} s, 1 thread)",
+            "all_threads": {"value": steps_all * N * L / el_all, "blas_threads": blas_threads,
+                            "sample": f"{steps_all} steps ({el_all:.1f} s)"},
+            "host": {"cpu_count": os.cpu_count(), "cpu_model": cpu_model()}}
 
 
-def load_traffic(workload, k, kind):
+def load_traffic(workload, k, kind, precision="f32"):
     """HBM bytes per launch of the dominant kernel measured with rocprofv3
-    counters (profiles/), or None when none was taken for this workload and
-    launch depth or the kernel sources changed since."""
+    counters (profiles/), or None when none was taken for this workload,
+    launch depth and message precision or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -253,6 +278,7 @@ def load_traffic(workload, k, kind):
         return None
     for e in t.get("entries", []):
         if (e.get("workload") == workload and e.get("steps_per_launch") == k
+                and e.get("precision", "f32") == precision
                 and e.get("kernel_source_sha256_16") == source_hash(kind)):
             return e.get("hbm_bytes_per_launch")
     return None
@@ -268,6 +294,8 @@ def main():
     ap.add_argument("--launches", type=int, default=200)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", default="f32", choices=["f32", "bf16", "f16"],
+                    help="neighbour-message precision (the state and the step stay FP32)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -296,8 +324,10 @@ def main():
     T = inst.iters
     log(f"workload {inst.name}: B={B} N={N} L={L} T={T} alpha={inst.alpha}")
     if args.workload.endswith("_adjoint"):
+        if args.precision != "f32":
+            sys.exit("the adjoint runs with FP32 messages only")
         return bench_adjoint(args, inst, torch, mf)
-    solver = make_solver(inst, torch, mf)
+    solver = make_solver(inst, torch, mf, precision=args.precision)
     q = torch.empty_like(solver.unary)
 
     if args.mode == "kernel":
@@ -332,9 +362,9 @@ def main():
 
     # dominant kernel: one step-kernel launch = K steps over all B * N * L node-labels
     mean_d, k = time_step_launches(solver, torch, args.launches)
-    algo = algorithmic_bytes(inst, k)
+    algo = algorithmic_bytes(inst, k, args.precision)
     achieved = algo / mean_d / 1e9
-    traffic = load_traffic(inst.name, k, source_kind(inst))
+    traffic = load_traffic(inst.name, k, source_kind(inst), args.precision)
     kname = step_kernel_name(inst, k)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -363,7 +393,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": workload_config(inst, "init + iters proximal steps + write q"),
+        "config": dict(workload_config(inst, "init + iters proximal steps + write q"), messages=args.precision),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
