@@ -10,9 +10,9 @@
 // Kernel A does everything up to Sb for one 64 x 4 tile (S needs the q halo),
 // kernel B the transposed stencil over Sb (needs the Sb halo) and the new g.
 // Theta_bar partials are per tile: mb and S of the tile's nodes are staged in
-// LDS and the L x L block product is formed there on the FP32 matrix cores,
-// then added to the tile's own FP64 accumulator (each workgroup owns its
-// slot, so there is no race).  After the last step the tile accumulators
+// LDS (over the q halo, which is dead by then) and the L x L block product is
+// formed there on the FP32 matrix cores, then added to the tile's own FP64
+// accumulator (each workgroup owns its slot, so there is no race).  After the last step the tile accumulators
 // are reduced in a fixed order: the sum runs over steps within a tile, then
 // over tiles, and is deterministic.
 #include <hip/hip_runtime.h>
@@ -42,9 +42,6 @@ __device__ inline AdjTile adj_tile(const AdjointArgs& a) {
 constexpr int AX = kTileX + 2;
 constexpr int AY = kTileY + 2;
 constexpr int AN = AX * AY;
-// Row stride of the m_bar / S staging in LDS: 4 words past the 256 nodes, so
-// that the 16 label rows a wavefront reads at once fall on distinct banks.
-constexpr int RS = kThreads + 4;
 // Tile partials of Theta_bar summed per stage-1 block.
 constexpr int kThetaChunk = 32;
 
@@ -79,13 +76,29 @@ __device__ __forceinline__ void load_halo(const float* __restrict__ src, float* 
   }
 }
 
+// At L = 21 the kernel fits 122 VGPRs and 35 KB of LDS: asking for four
+// waves per SIMD keeps the MFMA accumulator out of AGPRs, so four
+// workgroups share a CU (one wave of workgroups on the 16 x 128 x 128
+// batch).  Other label counts keep the compiler's choice.
 template <int LP, bool EXACT, int CONN, int COMPAT>
-__global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LP == 21 ? 4 : 1))) void adj_a_kernel(
+    AdjointArgs a) {
   constexpr int NB = (LP + 15) / 16;       // 16-label blocks of Theta_bar
-  __shared__ float qs[LP * AN];
-  __shared__ float ths[COMPAT == MF_COMPAT_GENERAL ? LP * LP : 1];
-  __shared__ float mbs[LP * RS];
-  __shared__ float Ss[LP * RS];
+  constexpr int NOB = NB * NB, WPB = 4 / NOB, KJ = kThreads / WPB;
+  // mb and S are staged in HS passes of HN nodes, so that the staging fits
+  // in the space of the q halo; the row stride is 4 words past HN, so the 16
+  // label rows a wavefront reads at once fall on distinct banks.
+  constexpr int HS = WPB == 1 ? 2 : 1;
+  constexpr int HN = kThreads / HS;
+  constexpr int RH = HN + 4;
+  constexpr int kU = LP * AN > 2 * LP * RH ? LP * AN : 2 * LP * RH;
+  __shared__ float lds_u[kU];
+  float* qs = lds_u;                       // q halo, then the staging
+  float* mbs = lds_u;
+  float* Ss = lds_u + LP * RH;
+  // Theta transposed, rows padded to 4: Theta^T mb reads contiguous rows
+  constexpr int TS = (LP + 3) & ~3;
+  __shared__ float ths[COMPAT == MF_COMPAT_GENERAL ? LP * TS : 1];
   __shared__ float red[NB == 1 ? 4 * 256 : 1];
   const int L = EXACT ? LP : a.L;
   const int N = a.N, H = a.H, W = a.W;
@@ -114,8 +127,8 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
   load_halo<LP, true>(a.ell_t + base, qs, L, N, H, W, x0, y0, tid);
   if (COMPAT == MF_COMPAT_GENERAL) {
 #pragma unroll
-    for (int f = tid; f < LP * LP; f += kThreads) {
-      const int l = f / LP, k = f - (f / LP) * LP;
+    for (int f = tid; f < LP * TS; f += kThreads) {
+      const int k = f / TS, l = f - (f / TS) * TS;
       ths[f] = (l < L && k < L) ? a.theta[l * L + k] : 0.f;
     }
   }
@@ -154,39 +167,44 @@ __global__ __launch_bounds__(kThreads) void adj_a_kernel(AdjointArgs a) {
           acc = a.potts_w * (tot - mb[k]);
         } else {
 #pragma unroll
-          for (int l = 0; l < LP; ++l) acc = fmaf(ths[l * LP + k], mb[l], acc);
+          for (int l = 0; l < LP; ++l) acc = fmaf(ths[k * TS + l], mb[l], acc);
         }
         a.s_bar[base + (size_t)k * N + n] = acc;
       }
     }
   }
-#pragma unroll
-  for (int l = 0; l < LP; ++l) {
-    mbs[l * RS + tid] = mb[l];
-    Ss[l * RS + tid] = S[l];
-  }
-  __syncthreads();
   // Theta_bar partial of this tile, P[l][k] = sum_n mb[l][n] S[k][n]: an
   // (L x 256) (256 x L) product on v_mfma_f32_16x16x4f32 with L padded to
   // 16 NB.  Lane x of a wavefront reads A[x % 16][x / 16] = mb[row][node]
   // and B[x / 16][x % 16] = S[col][node] and holds rows 4 (x / 16) + i,
   // column x % 16 of the output block.  With NB = 2 each of the four
-  // wavefronts owns one 16 x 16 output block; with NB = 1 they split the
-  // 256 nodes and their sums are added in a fixed order.
+  // wavefronts owns one 16 x 16 output block and runs over the nodes in two
+  // staged passes (the same accumulation order as one pass); with NB = 1
+  // they split the 256 nodes and their sums are added in a fixed order.
   {
-    constexpr int NOB = NB * NB, WPB = 4 / NOB, KJ = kThreads / WPB;
     const int wave = tid >> 6, lane = tid & 63;
     const int ob = wave / WPB, kpart = wave - ob * WPB;
     const int rb = ob / NB, cb = ob - rb * NB;
     const int la = 16 * rb + (lane & 15), kc = 16 * cb + (lane & 15);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     const int j0 = kpart * KJ + (lane >> 4);
+    for (int h = 0; h < HS; ++h) {
+      __syncthreads();   // h = 0: the q halo is dead; h = 1: the first pass is read
+      if (tid / HN == h) {
+#pragma unroll
+        for (int l = 0; l < LP; ++l) {
+          mbs[l * RH + tid - h * HN] = mb[l];
+          Ss[l * RH + tid - h * HN] = S[l];
+        }
+      }
+      __syncthreads();
 #pragma unroll 8
-    for (int kb = 0; kb < KJ / 4; ++kb) {
-      const int j = j0 + 4 * kb;
-      const float av = la < LP ? mbs[la * RS + j] : 0.f;
-      const float bv = kc < LP ? Ss[kc * RS + j] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      for (int kb = 0; kb < KJ / 4 / HS; ++kb) {
+        const int j = j0 + 4 * kb;
+        const float av = la < LP ? mbs[la * RH + j] : 0.f;
+        const float bv = kc < LP ? Ss[kc * RH + j] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      }
     }
     const size_t part = (size_t)tile.t;
     double* out = a.theta_tile + part * L * L;
