@@ -222,7 +222,13 @@ __device__ inline void rule_epilogue(const StepArgs& a, const RuleArgs& rx, cons
 // RULE selects the update made from the messages m (mf_rule); every rule but
 // MF_RULE_FIXED runs one lane per node and takes its extra state and
 // constants from rx.
-template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY, int RULE = MF_RULE_FIXED>
+//
+// STREAM marks the unaries and the new state as streams (non-temporal load and
+// store): on grids whose arrays cannot stay in the last-level cache between
+// steps they are read or written once per step, and keeping them out of the
+// cache leaves it to the halo rows that neighbouring tiles share.
+template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY, int RULE = MF_RULE_FIXED,
+          bool STREAM = false>
 __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b, int x0, int y0,
                                  Smem<LG, LPN, TX, TY, PREC>& sm, const RuleArgs* rx = nullptr) {
   static_assert(RULE == MF_RULE_FIXED || LPN == 1, "step rules run one lane per node");
@@ -256,7 +262,8 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
     valid[j] = l < L;
     const unsigned lc = (unsigned)(l < L ? l : L - 1);
     ell[j] = lin[lc * N + n];
-    uu[j] = ug[lc * N + n];
+    if constexpr (STREAM) uu[j] = __builtin_nontemporal_load(&ug[lc * N + n]);
+    else uu[j] = ug[lc * N + n];
   }
   float hv[HREG];
 #pragma unroll
@@ -368,7 +375,10 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
 #pragma unroll
   for (int j = 0; j < LG; ++j) {
     const int l = sub * LG + j;
-    if (valid[j]) out[(unsigned)l * N + n] = z[j] - lse;
+    if (valid[j]) {
+      if constexpr (STREAM) __builtin_nontemporal_store(z[j] - lse, &out[(unsigned)l * N + n]);
+      else out[(unsigned)l * N + n] = z[j] - lse;
+    }
   }
 }
 
@@ -386,7 +396,7 @@ __device__ inline int xcd_tile(int w, int total) {
   return x * q + (x < r ? x : r) + w / kXcds;
 }
 
-template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY>
+template <int LG, int LPN, int LC, int CONN, int COMPAT, int PREC, int TX, int TY, bool STREAM>
 __global__ __launch_bounds__(TX * TY * LPN) void step_kernel(StepArgs a, float one_minus_alpha) {
   __shared__ Smem<LG, LPN, TX, TY, PREC> sm;
   const int tiles_x = (a.W + TX - 1) / TX, tiles_y = (a.H + TY - 1) / TY;
@@ -395,7 +405,8 @@ __global__ __launch_bounds__(TX * TY * LPN) void step_kernel(StepArgs a, float o
   const int b = t / per_item;
   const int r = t - b * per_item;
   const int ty = r / tiles_x, tx = r - ty * tiles_x;
-  tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY>(a, one_minus_alpha, b, tx * TX, ty * TY, sm);
+  tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY, MF_RULE_FIXED, STREAM>(a, one_minus_alpha, b, tx * TX, ty * TY,
+                                                                            sm);
 }
 
 // Many independent problems in one launch: slot k owns tiles
@@ -431,6 +442,14 @@ inline int slots_for(int L) {
   return L == 2 ? 2 : L == 21 ? 21 : L <= 4 ? 4 : L <= 8 ? 8 : L <= 16 ? 16 : 32;
 }
 
+// The unaries and both state planes of one step (12 B per node-label) exceed
+// the 256 MB last-level cache: nothing of them survives to the next step, so
+// the step kernel streams the unaries and the new state past the cache.
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
+inline bool streams_past_cache(const StepArgs& a) {
+  return (size_t)12 * a.B * a.L * a.N > kLastLevelCacheBytes;
+}
+
 inline int tiles(int B, int H, int W, int L) {
   (void)L;
   return B * ((W + 63) / 64) * ((H + 3) / 4);
@@ -446,24 +465,31 @@ hipError_t launch_many_f16(const ManyArgs& m, int L, int conn, int compat, hipSt
 // Instantiation helper used by the per-precision translation units.
 template <int PREC>
 struct ForPrec {
-  template <int LG, int LPN, int LC, int TX, int TY>
-  static hipError_t one(const StepArgs& a, int conn, int compat, hipStream_t s) {
+  template <int LG, int LPN, int LC, int TX, int TY, bool STREAM>
+  static hipError_t one_s(const StepArgs& a, int conn, int compat, hipStream_t s) {
     // one-dimensional grid: step_kernel maps workgroups to tiles XCD by XCD
     dim3 grid(((a.W + TX - 1) / TX) * ((a.H + TY - 1) / TY) * a.B);
     dim3 block(TX * TY * LPN);
     const float om = (float)(1.0 - (double)a.alpha);
     if (conn == 4) {
       if (compat == MF_COMPAT_POTTS)
-        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 4, MF_COMPAT_POTTS, PREC, TX, TY>), grid, block, 0, s, a, om);
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 4, MF_COMPAT_POTTS, PREC, TX, TY, STREAM>), grid, block, 0, s, a, om);
       else
-        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 4, MF_COMPAT_GENERAL, PREC, TX, TY>), grid, block, 0, s, a, om);
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 4, MF_COMPAT_GENERAL, PREC, TX, TY, STREAM>), grid, block, 0, s, a,
+                           om);
     } else {
       if (compat == MF_COMPAT_POTTS)
-        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 8, MF_COMPAT_POTTS, PREC, TX, TY>), grid, block, 0, s, a, om);
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 8, MF_COMPAT_POTTS, PREC, TX, TY, STREAM>), grid, block, 0, s, a, om);
       else
-        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 8, MF_COMPAT_GENERAL, PREC, TX, TY>), grid, block, 0, s, a, om);
+        hipLaunchKernelGGL((step_kernel<LG, LPN, LC, 8, MF_COMPAT_GENERAL, PREC, TX, TY, STREAM>), grid, block, 0, s, a,
+                           om);
     }
     return hipGetLastError();
+  }
+  template <int LG, int LPN, int LC, int TX, int TY>
+  static hipError_t one(const StepArgs& a, int conn, int compat, hipStream_t s) {
+    return streams_past_cache(a) ? one_s<LG, LPN, LC, TX, TY, true>(a, conn, compat, s)
+                                 : one_s<LG, LPN, LC, TX, TY, false>(a, conn, compat, s);
   }
   template <int LG, int LPN, int LC, int TX, int TY>
   static hipError_t many(const ManyArgs& m, int conn, int compat, hipStream_t s) {
