@@ -31,10 +31,10 @@
 // j range; its eight wavefronts split the slice's 32-column chunks and each
 // accumulates the whole 64 x 32 (rows x labels, L padded to 32) tile in
 // registers.  Slices write FP32 partial sums.  A second kernel, one
-// workgroup per 64-row block, adds the KS partials in a fixed order and
-// runs the per-node step, so the result is deterministic; it also writes
-// the next Q planes and the block's column sums of q, which the
-// co-occurrence term of the next step reduces in a fixed order.  The
+// workgroup per 16 nodes, adds the KS partials in a fixed order and runs
+// the per-node step, so the result is deterministic; it also writes the
+// next Q planes and the block's column sums of q, which the co-occurrence
+// term of the next step reduces in a fixed order.  The
 // hand-off between the two is the kernel boundary: the eight XCDs of the
 // MI355X have separate L2 caches, and a device-scope fence per workgroup
 // (to hand the partials to a last-arriving workgroup inside one kernel)
@@ -58,25 +58,6 @@ __device__ inline unsigned short f2bf_rne(float x) {
   return (unsigned short)(u >> 16);
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
-
-// Sum over the 64 lanes in the VALU, one fixed order: rotations by 8, 4, 2
-// and 1 within each row of 16 lanes (DPP), then rows 0 + 1 and 2 + 3
-// (v_permlane16_swap) and the two half-waves (v_permlane32_swap).  Lane 0
-// holds the sum.
-template <int N>
-__device__ inline float row_ror(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + N, 0xF, 0xF, false));
-}
-__device__ inline float wave_sum_dpp(float v) {
-  v += row_ror<8>(v);
-  v += row_ror<4>(v);
-  v += row_ror<2>(v);
-  v += row_ror<1>(v);
-  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
 
 // K_ij = exp(-|f_i - f_j|^2 / 2) in FP32, K_ii = 0, rounded to BF16 (nearest even).
 __global__ __launch_bounds__(256) void dense_kernel_build(const float* __restrict__ f, int n, int dim,
@@ -131,22 +112,43 @@ __global__ __launch_bounds__(256) void dense_tile_k_kernel(const unsigned short*
   Kt[c] = v;
 }
 
-// q^0 planes and per-block column sums from the initial state.  One
-// wavefront per 64-node block; lane = node.
-template <int NS>
-__global__ __launch_bounds__(64) void dense_prepare_kernel(DenseStepArgs a) {
-  const int rb = blockIdx.x, b = blockIdx.y;
-  const int lane = threadIdx.x;
-  const int i = rb * kRB + lane;
-  const int L = a.L, N = a.N, Np = a.Np;
-  unsigned short* planes = a.q_out + (size_t)b * NS * kLP * Np;
-  for (int l = 0; l < kLP; ++l) {
-    float q = 0.f;
-    if (i < N && l < L) q = __expf(a.state_in[((size_t)b * L + l) * N + i]);
-    store_planes<NS>(planes, l, i, q);
-    const float t = wave_sum_dpp(q);
-    if (lane == 0) a.t_out[((size_t)b * a.NRB + rb) * kLP + l] = t;
+// The per-node kernels (q^0 planes, and the step after the product) take
+// kEB = 16 nodes per workgroup: wavefront w holds nodes 2w and 2w + 1 of the
+// block, lane x node 2w + x / 32 and label slot x % 32.  A node's labels
+// are then one half-wave, so its max and sum reduce with an xor butterfly
+// of shuffles (the two lanes of a pair add the same operands, so every lane
+// gets a bitwise-identical total), and N = 4096 gives 256 workgroups.
+constexpr int kEB = 16;                  // nodes per workgroup
+constexpr int kNT = 64 * kEB / 2;        // threads: eight wavefronts of two nodes
+constexpr int kQSt = kLP + 1;            // LDS row stride (conflict-free across the label lanes)
+
+// Column sums of q over the block's 16 nodes in node order: each wavefront's
+// pair first, then the wavefronts in order.  Every thread calls it.
+__device__ inline void block_col_sums(float q, float* __restrict__ red, float* __restrict__ t_row, int tid) {
+  const int wave = tid >> 6, lane = tid & 63;
+  const float pair = q + __shfl_xor(q, 32);
+  if (lane < kLP) red[wave * kLP + lane] = pair;
+  __syncthreads();
+  if (tid < kLP) {
+    float t = red[tid];
+#pragma unroll
+    for (int w = 1; w < kNT / 64; ++w) t += red[w * kLP + tid];
+    t_row[tid] = t;
   }
+}
+
+// q^0 planes and the blocks' column sums from the initial state.
+template <int NS>
+__global__ __launch_bounds__(kNT) void dense_prepare_kernel(DenseStepArgs a) {
+  __shared__ float red[kNT / 64 * kLP];
+  const int eb = blockIdx.x, b = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, l = lane & 31;
+  const int i = eb * kEB + 2 * (tid >> 6) + (lane >> 5);
+  const int L = a.L, N = a.N;
+  float q = 0.f;
+  if (i < N && l < L) q = __expf(a.state_in[((size_t)b * L + l) * N + i]);
+  store_planes<NS>(a.q_out + (size_t)b * NS * kLP * a.Np, l, i, q);
+  block_col_sums(q, red, a.t_out + ((size_t)b * a.NEB + eb) * kLP, tid);
 }
 
 // One workgroup: the 64-row block rb against the j slice ks.  Each of the
@@ -239,178 +241,109 @@ __global__ __launch_bounds__(64 * kStepWaves) void dense_step_kernel(DenseStepAr
   }
 }
 
-// The per-node step of one 64-row block: the KS partial sums of S in a fixed
-// order, the message, the step, the next Q planes and the block's column
-// sums of q.  kEpiGroups wavefronts: lane = node of the block, wavefront
-// w = label group (labels w + kEpiGroups j).  The partials arrive node-major and are
-// transposed through LDS (coalesced loads); the terms that mix labels
-// (Theta S, the co-occurrence product, the per-node max and sum) read the
-// node's other labels from LDS.  LC > 0 fixes L at compile time so the
-// label loops unroll; every global load is issued before the first wait.
-constexpr int kEpiGroups = 8;                 // label groups (wavefronts) per 64-node block:
-                                              // 8 measured faster than 4 (shorter per-thread chains)
-constexpr int kEpiThreads = 64 * kEpiGroups;
-constexpr int kSt = kLP + 1;          // LDS row stride of the node x label tiles
-constexpr int kTParts = kEpiThreads / kLP;
-
+// The per-node step of 16 nodes (mapping as for dense_prepare_kernel): the
+// KS partial sums of S in slice order (node-major, so a wavefront's loads
+// are 256 contiguous bytes), the message, the step, the next Q planes and
+// the block's column sums of q.  The terms that mix labels (Theta S, the
+// co-occurrence product) read the node's S and q rows from LDS; Theta and C
+// are staged there too.  LC > 0 fixes L at compile time so the label loops
+// unroll.
 template <int NS, int COMPAT, bool COOC, int LC>
-__global__ __launch_bounds__(kEpiThreads) void dense_epilogue_kernel(DenseStepArgs a, float one_minus_alpha) {
-  const int rb = blockIdx.x, b = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // label group, uniform in the wavefront
-  const int L = LC > 0 ? LC : a.L, N = a.N, Np = a.Np;
-  __shared__ float Th[kLP * kLP];      // Theta (general), rows of stride 32
-  __shared__ float Cc[kLP * kLP];      // co-occurrence
-  __shared__ float St[kRB * kSt];      // S[node][label]
-  __shared__ float Qt[kRB * kSt];      // q[node][label] (co-occurrence)
-  __shared__ float red[kEpiGroups * kRB];   // per-node partials of the label groups
-  __shared__ float Tp[kEpiThreads];    // partial column sums of q at the previous step
+__global__ __launch_bounds__(kNT) void dense_epilogue_kernel(DenseStepArgs a, float one_minus_alpha) {
+  constexpr bool GEN = COMPAT != MF_COMPAT_POTTS;
+  __shared__ float Th[GEN ? kLP * kQSt : 1];        // Theta (general)
+  __shared__ float Cc[COOC ? kLP * kQSt : 1];       // co-occurrence
+  __shared__ float Sr[kEB * kQSt];                  // S rows of the block's nodes
+  __shared__ float Qr[COOC ? kEB * kQSt : 1];       // q rows (co-occurrence)
+  __shared__ float Tp[COOC ? kNT : 1];              // partial column sums of q at the previous step
   __shared__ float Ts[kLP];
-
-  const int i = rb * kRB + lane;
-  const bool inside = i < N;
-  const size_t base = (size_t)b * L * N + (inside ? i : 0);
-  constexpr int NG = kEpiGroups, J = kLP / NG;
-  // per-node total over the label groups, in one fixed order
-  auto group_sum = [&]() {
-    float v = red[lane];
-#pragma unroll
-    for (int g = 1; g < NG; ++g) v += red[g * kRB + lane];
-    return v;
-  };
-  float ell[J], un[J], z[J];
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int l = w + NG * j;
-    const bool on = inside && l < L;
-    ell[j] = on ? a.state_in[base + (size_t)l * N] : 0.f;
-    un[j] = on ? a.unary[base + (size_t)l * N] : 0.f;
-  }
-  if (COMPAT != MF_COMPAT_POTTS)
-    for (int f = tid; f < L * L; f += kEpiThreads) Th[(f / L) * kLP + f % L] = a.theta[f];
-  if (COOC)
-    for (int f = tid; f < L * L; f += kEpiThreads) Cc[(f / L) * kLP + f % L] = a.cooc[f];
+  __shared__ float red[kNT / 64 * kLP];
+  const int eb = blockIdx.x, b = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, l = lane & 31;
+  const int nl = 2 * (tid >> 6) + (lane >> 5);      // node within the block
+  const int i = eb * kEB + nl;
+  const int L = LC > 0 ? LC : a.L, N = a.N, Np = a.Np;
+  const bool valid = i < N && l < L;
+  // every global load is issued before the first wait; addresses are clamped
+  const size_t at = ((size_t)b * L + (l < L ? l : L - 1)) * N + (i < N ? i : N - 1);
+  const float ell = a.state_in[at];
+  const float un = a.unary[at];
+  if (GEN)
+    for (int f = tid; f < L * L; f += kNT) Th[(f / L) * kQSt + f % L] = a.theta[f];
   if (COOC) {
-    // column sums: label tid % 32, blocks tid / 32 + 8 k in order
-    const int l = tid % kLP;
+    for (int f = tid; f < L * L; f += kNT) Cc[(f / L) * kQSt + f % L] = a.cooc[f];
+    // column sums: label tid % 32, blocks tid / 32 + 16 k in order
+    const int lt = tid % kLP;
     float t = 0.f;
-#pragma unroll 8
-    for (int k = tid / kLP; k < a.NRB; k += kTParts) t += a.t_in[((size_t)b * a.NRB + k) * kLP + l];
+#pragma unroll 4
+    for (int k = tid / kLP; k < a.NEB; k += kNT / kLP) t += a.t_in[((size_t)b * a.NEB + k) * kLP + lt];
     Tp[tid] = t;
   }
-  // S = sum over the KS slices, element by element in slice order
+  float S = 0.f;
   {
-    const float* sp = a.s_part + ((size_t)b * a.KS * Np + (size_t)rb * kRB) * kLP;
-    float acc[kRB * kLP / kEpiThreads];
-#pragma unroll
-    for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) acc[r] = 0.f;
+    const float* sp = a.s_part + ((size_t)b * a.KS * Np + i) * kLP + l;
 #pragma unroll 8
-    for (int k = 0; k < a.KS; ++k) {
-#pragma unroll
-      for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) acc[r] += sp[(size_t)k * Np * kLP + tid + r * kEpiThreads];
-    }
-#pragma unroll
-    for (int r = 0; r < kRB * kLP / kEpiThreads; ++r) {
-      const int f = tid + r * kEpiThreads;
-      St[(f / kLP) * kSt + (f % kLP)] = acc[r];
-    }
+    for (int k = 0; k < a.KS; ++k) S += sp[(size_t)k * Np * kLP];
   }
-  if (COOC) {
-#pragma unroll
-    for (int j = 0; j < J; ++j) Qt[lane * kSt + w + NG * j] = (inside && w + NG * j < L) ? __expf(ell[j]) : 0.f;
-  }
+  Sr[nl * kQSt + l] = S;
+  if (COOC) Qr[nl * kQSt + l] = valid ? __expf(ell) : 0.f;
   __syncthreads();
   if (COOC && tid < kLP) {
     float t = 0.f;
 #pragma unroll
-    for (int p = 0; p < kTParts; ++p) t += Tp[p * kLP + tid];
+    for (int p = 0; p < kNT / kLP; ++p) t += Tp[p * kLP + tid];
     Ts[tid] = t;
   }
+  if (COOC) __syncthreads();
 
-  float tot = 0.f;
-  if (COMPAT == MF_COMPAT_POTTS) {
-    float part = 0.f;
+  const float* srow = Sr + nl * kQSt;
+  float m = un;
+  if (!GEN) {
+    float tot = 0.f;
+    if constexpr (LC > 0) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) part += (w + NG * j < L) ? St[lane * kSt + w + NG * j] : 0.f;
-    red[w * kRB + lane] = part;
-  }
-  __syncthreads();
-  if (COMPAT == MF_COMPAT_POTTS) tot = group_sum();
-  // the node's S and q rows, read once
-  float srow[kLP], qrow[kLP];
-  if (COMPAT != MF_COMPAT_POTTS) {
-#pragma unroll
-    for (int k = 0; k < kLP; ++k) srow[k] = (LC == 0 || k < L) ? St[lane * kSt + k] : 0.f;
-  }
-  if (COOC) {
-#pragma unroll
-    for (int k = 0; k < kLP; ++k) qrow[k] = (LC == 0 || k < L) ? Ts[k] - Qt[lane * kSt + k] : 0.f;
-  }
-  float mx = -INFINITY;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int l = w + NG * j;
-    z[j] = -INFINITY;
-    if (l < L) {
-      float m = un[j];
-      if (COMPAT == MF_COMPAT_POTTS) {
-        m += a.potts_w * (tot - St[lane * kSt + l]);
-      } else {
-        float acc = 0.f;
-        if constexpr (LC > 0) {
-#pragma unroll
-          for (int k = 0; k < LC; ++k) acc = fmaf(Th[l * kLP + k], srow[k], acc);
-        } else {
-          for (int k = 0; k < L; ++k) acc = fmaf(Th[l * kLP + k], St[lane * kSt + k], acc);
-        }
-        m += acc;
-      }
-      if (COOC) {
-        float c = 0.f;
-        if constexpr (LC > 0) {
-#pragma unroll
-          for (int k = 0; k < LC; ++k) c = fmaf(Cc[l * kLP + k], qrow[k], c);
-        } else {
-          for (int k = 0; k < L; ++k) c = fmaf(Cc[l * kLP + k], Ts[k] - Qt[lane * kSt + k], c);
-        }
-        m += c * a.inv_n;
-      }
-      z[j] = one_minus_alpha * ell[j] - a.alpha * m;
-      mx = fmaxf(mx, z[j]);
+      for (int k = 0; k < LC; ++k) tot += srow[k];
+    } else {
+      for (int k = 0; k < L; ++k) tot += srow[k];
     }
-  }
-  // per-node max and sum over the label groups, fixed order
-  __syncthreads();
-  red[w * kRB + lane] = mx;
-  __syncthreads();
-  mx = red[lane];
+    m += a.potts_w * (tot - S);
+  } else if (l < L) {
+    const float* th = Th + l * kQSt;
+    float acc = 0.f;
+    if constexpr (LC > 0) {
 #pragma unroll
-  for (int g = 1; g < NG; ++g) mx = fmaxf(mx, red[g * kRB + lane]);
-  __syncthreads();
-  float e[J];
-  float se = 0.f;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    e[j] = (w + NG * j < L) ? __expf(z[j] - mx) : 0.f;
-    se += e[j];
+      for (int k = 0; k < LC; ++k) acc = fmaf(th[k], srow[k], acc);
+    } else {
+      for (int k = 0; k < L; ++k) acc = fmaf(th[k], srow[k], acc);
+    }
+    m += acc;
   }
-  red[w * kRB + lane] = se;
-  __syncthreads();
-  se = group_sum();
+  if (COOC && l < L) {
+    const float* cr = Cc + l * kQSt;
+    const float* qrow = Qr + nl * kQSt;
+    float c = 0.f;
+    if constexpr (LC > 0) {
+#pragma unroll
+      for (int k = 0; k < LC; ++k) c = fmaf(cr[k], Ts[k] - qrow[k], c);
+    } else {
+      for (int k = 0; k < L; ++k) c = fmaf(cr[k], Ts[k] - qrow[k], c);
+    }
+    m += c * a.inv_n;
+  }
+  const float z = valid ? one_minus_alpha * ell - a.alpha * m : -INFINITY;
+  // per-node max and sum over the node's half-wave
+  float mx = z;
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 32));
+  const float e = valid ? __expf(z - mx) : 0.f;
+  float se = e;
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) se += __shfl_xor(se, off, 32);
   const float lse = mx + __logf(se);
-  const float inv = 1.0f / se;
-  unsigned short* planes = a.q_out + (size_t)b * NS * kLP * Np;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int l = w + NG * j;
-    const float q = inside ? e[j] * inv : 0.f;
-    if (inside && l < L) a.state_out[base + (size_t)l * N] = z[j] - lse;
-    store_planes<NS>(planes, l, i, q);
-    if (COOC) {
-      const float t = wave_sum_dpp(q);
-      if (lane == 0) a.t_out[((size_t)b * a.NRB + rb) * kLP + l] = t;
-    }
-  }
+  const float q = valid ? e * (1.0f / se) : 0.f;
+  if (valid) a.state_out[at] = z - lse;
+  store_planes<NS>(a.q_out + (size_t)b * NS * kLP * Np, l, i, q);
+  if (COOC) block_col_sums(q, red, a.t_out + ((size_t)b * a.NEB + eb) * kLP, tid);
 }
 
 // FP64 free energy.  qd[b][j][l] = exp(log q) in FP64 (node-major).
@@ -491,14 +424,14 @@ __global__ __launch_bounds__(256) void dense_fe_kernel(DenseFreeEnergyArgs a) {
 
 template <int NS, int LC>
 hipError_t epilogue_lc(const DenseStepArgs& a, int compat, float om, hipStream_t s) {
-  const dim3 grid(a.NRB, a.B);
+  const dim3 grid(a.NEB, a.B);
   const bool cooc = a.cooc != nullptr;
   if (compat == MF_COMPAT_POTTS) {
-    if (cooc) hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_POTTS, true, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
-    else hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_POTTS, false, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
+    if (cooc) hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_POTTS, true, LC>), grid, dim3(kNT), 0, s, a, om);
+    else hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_POTTS, false, LC>), grid, dim3(kNT), 0, s, a, om);
   } else {
-    if (cooc) hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_GENERAL, true, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
-    else hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_GENERAL, false, LC>), grid, dim3(kEpiThreads), 0, s, a, om);
+    if (cooc) hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_GENERAL, true, LC>), grid, dim3(kNT), 0, s, a, om);
+    else hipLaunchKernelGGL((dense_epilogue_kernel<NS, MF_COMPAT_GENERAL, false, LC>), grid, dim3(kNT), 0, s, a, om);
   }
   return hipGetLastError();
 }
@@ -521,6 +454,7 @@ DenseGeometry dense_geometry(int N, int B) {
   DenseGeometry g;
   g.Np = (N + kRB - 1) / kRB * kRB;
   g.NRB = g.Np / kRB;
+  g.NEB = g.Np / kEB;
   // slices of the j range: enough workgroups to cover the compute units,
   // each slice at least 256 columns wide
   int ks = (512 + g.NRB * B - 1) / (g.NRB * B);
@@ -546,11 +480,11 @@ hipError_t launch_dense_kernel(const float* f, int n, int dim, uint16_t* K, hipS
 }
 
 hipError_t launch_dense_prepare(const DenseStepArgs& a, int NS, hipStream_t s) {
-  dim3 grid(a.NRB, a.B);
+  dim3 grid(a.NEB, a.B);
   switch (NS) {
-    case 3: hipLaunchKernelGGL(dense_prepare_kernel<3>, grid, dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(dense_prepare_kernel<2>, grid, dim3(64), 0, s, a); break;
-    default: hipLaunchKernelGGL(dense_prepare_kernel<1>, grid, dim3(64), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(dense_prepare_kernel<3>, grid, dim3(kNT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(dense_prepare_kernel<2>, grid, dim3(kNT), 0, s, a); break;
+    default: hipLaunchKernelGGL(dense_prepare_kernel<1>, grid, dim3(kNT), 0, s, a); break;
   }
   return hipGetLastError();
 }

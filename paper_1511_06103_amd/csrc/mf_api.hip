@@ -65,7 +65,7 @@ mf::WorkspaceLayout layout_for(const mf_desc& d) {
     w.ds = off;
     off += align256(sizeof(float) * B * (size_t)w.dg.KS * Np * 32);
     w.dt = off;
-    off += align256(sizeof(float) * 2 * B * (size_t)w.dg.NRB * 32);
+    off += align256(sizeof(float) * 2 * B * (size_t)w.dg.NEB * 32);
     w.dqd = off;
     off += align256(sizeof(double) * B * (size_t)d.n_nodes * (size_t)d.n_labels);
   }
@@ -174,7 +174,7 @@ mf::DenseStepArgs dense_args(const mf_handle* h, int from) {
   const mf::WorkspaceLayout& w = h->ws;
   const size_t B = (size_t)d.batch, Np = (size_t)w.dg.Np;
   const size_t plane_elems = B * (size_t)w.dense_ns * 32 * Np;
-  const size_t t_elems = B * (size_t)w.dg.NRB * 32;
+  const size_t t_elems = B * (size_t)w.dg.NEB * 32;
   const size_t elems = B * d.n_labels * d.n_nodes;
   mf::DenseStepArgs a;
   a.K = d.dense_K;
@@ -195,6 +195,7 @@ mf::DenseStepArgs dense_args(const mf_handle* h, int from) {
   a.Np = w.dg.Np;
   a.KS = w.dg.KS;
   a.NRB = w.dg.NRB;
+  a.NEB = w.dg.NEB;
   a.jchunk = w.dg.jchunk;
   a.alpha = (float)d.alpha;
   a.potts_w = d.potts_w;

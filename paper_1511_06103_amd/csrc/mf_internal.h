@@ -86,11 +86,11 @@ struct DenseStepArgs {
   const uint16_t* q_in;    // [B][Np/32][NS][2][64 lanes][8] bf16 planes of q(state_in)
   uint16_t* q_out;         // planes of q(state_out)
   float* s_part;           // [B][KS][Np][32] partial S
-  const float* t_in;       // [B][NRB][32] column sums of q(state_in) per row block
+  const float* t_in;       // [B][NEB][32] column sums of q(state_in) per 16-node block
   float* t_out;
   const float* theta;      // [L][L] (general)
   const float* cooc;       // [L][L] or nullptr
-  int B, L, N, Np, KS, NRB, jchunk;
+  int B, L, N, Np, KS, NRB, NEB, jchunk;
   float alpha, potts_w, inv_n;
 };
 
@@ -124,7 +124,7 @@ struct LipArgs {
 };
 
 struct DenseGeometry {
-  int Np = 0, NRB = 0, KS = 0, jchunk = 0;
+  int Np = 0, NRB = 0, NEB = 0, KS = 0, jchunk = 0;   // NEB: 16-node blocks of the per-node kernels
 };
 
 struct DenseFreeEnergyArgs {
