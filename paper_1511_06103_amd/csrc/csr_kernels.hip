@@ -214,8 +214,9 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
 #pragma unroll
     for (int u = 0; u < LH; ++u) {
       float acc = 0.f;
+      // with L compiled in, the columns past L (zero in Th) are left out
 #pragma unroll
-      for (int k = 0; k < LQ; ++k) acc = fmaf(Th[(l0 + u) * LQ + k], Sa[k], acc);
+      for (int k = 0; k < (LC > 0 ? LC : LQ); ++k) acc = fmaf(Th[(l0 + u) * LQ + k], Sa[k], acc);
       z[u] = one_minus_alpha * ell[u] - a.alpha * (uu[u] + acc);
     }
   }

@@ -62,6 +62,27 @@ def test_csr_one_step_from_identical_state():
     assert cases.max_dq(gpu_state(s)[0], ref) <= 1e-6
 
 
+def test_csr_bench_size_one_step_and_end_to_end():
+    """The benchmark's general graph at its own size (65536 nodes, average
+    degree 8, weighted, L = 21, the same seed): one step from an identical
+    state, and ten steps from the initialisation, against the oracle on
+    every node-label."""
+    inst = synth.csr_instance(8, 65536, 21, avg_degree=8, weighted=True, alpha=0.5, iters=100, name="csr65536_L21")
+    model = cases.oracle_model(inst)
+    traj = O.solve(model, 0.5, 10)
+    start = traj[7].astype(np.float32)
+    B, L, N = inst.unary.shape
+    st = torch.empty((2, B, L, N), dtype=torch.float32, device="cuda:0")
+    st[0].copy_(torch.from_numpy(start[None]))
+    s = cases.gpu_solver(inst, init="state", state=st)
+    s.step(1)
+    assert cases.max_dq(gpu_state(s)[0], O.prox_step(start.astype(np.float64), model, 0.5)) <= 1e-6
+    s = cases.gpu_solver(inst)
+    s.step(10)
+    assert cases.max_dq(gpu_state(s)[0], traj[10]) <= 1e-5
+    s.check()
+
+
 def mean_dq(a, b):
     return float(np.abs(np.exp(a) - np.exp(b)).mean())
 
