@@ -2,9 +2,12 @@
 
 Requests carry a grid problem (unaries, Theta, size, alpha, iterations).
 They arrive over time, wait in a FIFO queue and are admitted while their
-device-memory footprint fits a budget.  Every scheduler tick advances all
-admitted problems by one proximal step through ``mf_step_many``: one launch
-per label count, tiles of every problem in the same launch.  A problem that
+device-memory footprint fits a budget (optionally at most a fixed number
+per scheduler tick, so that stepping starts while later requests are still
+uploading).
+Every tick advances all admitted problems by one proximal step (optionally
+a few) through ``mf_step_many``: one launch per label count and group of up
+to 48 problems, tiles of every problem of the group in the same launch.  A problem that
 reaches its iteration count has q written out and copied to pinned host
 memory asynchronously; its memory returns to the budget when the copy has
 landed, and queued requests are admitted at the next tick.  Work of newly
@@ -108,11 +111,17 @@ class Server:
     """Admission by device-memory footprint, one batched launch per tick."""
 
     def __init__(self, budget_bytes: int = 64 << 30, precision: str = "bf16", device: str = "cuda:0",
-                 max_ahead_ticks: int = 2):
+                 max_ahead_ticks: int = 2, admit_per_tick: int = 0, steps_per_tick: int = 1):
         self.budget = int(budget_bytes)
         self.precision = precision
         self.device = torch.device(device)
         self.max_ahead = max_ahead_ticks
+        # admissions per tick (0: all that fit), so that stepping starts while
+        # later requests are still uploading
+        self.admit_per_tick = int(admit_per_tick)
+        # steps per tick: the active problems advance together by up to this
+        # many steps, never past the one closest to its iteration count
+        self.steps_per_tick = max(1, int(steps_per_tick))
         self.used = 0
         self.queue: List[SolveRequest] = []
         self.active: List[_Slot] = []
@@ -137,7 +146,11 @@ class Server:
         self.stats.n_rejected += 1
 
     def _admit(self, now):
+        n = 0
         while self.queue and self.used + footprint_bytes(self.queue[0]) <= self.budget:
+            if self.admit_per_tick and n >= self.admit_per_tick:
+                break
+            n += 1
             req = self.queue.pop(0)
             nb = footprint_bytes(req)
             u = torch.from_numpy(req.unary).pin_memory().to(self.device, non_blocking=True)
@@ -198,7 +211,8 @@ class Server:
                 i += 1
             self._admit(now)
             if self.active:
-                mf.step_many([s.solver for s in self.active], 1)
+                k = min(self.steps_per_tick, min(s.req.iters - s.solver.iteration for s in self.active))
+                mf.step_many([s.solver for s in self.active], k)
                 self.stats.ticks += 1
                 ev = torch.cuda.Event()
                 ev.record()
@@ -258,7 +272,10 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--saturation", action="store_true", help="also replay all requests at t = 0 and "
                     "compare with solving them one by one")
+    ap.add_argument("--admit-per-tick", type=int, default=0, help="admissions per scheduler tick (0: all that fit)")
+    ap.add_argument("--steps-per-tick", type=int, default=1)
     args = ap.parse_args(argv)
+    sched = dict(admit_per_tick=args.admit_per_tick, steps_per_tick=args.steps_per_tick)
     from . import synth
     trace = synth.serving_trace(4, args.n, args.rate)
     print(f"generating {args.n} requests", file=sys.stderr, flush=True)
@@ -270,13 +287,13 @@ def main(argv=None):
     solve_alone(warm[0], args.precision)
     out = {"workload": f"serving: {args.n} requests, Poisson {args.rate}/s, sides 64-512, L in {{2, 21}}, "
                        f"{args.iters} iterations, {args.precision} messages"}
-    srv = Server(budget_bytes=args.budget_mib << 20, precision=args.precision)
+    srv = Server(budget_bytes=args.budget_mib << 20, precision=args.precision, **sched)
     st = srv.run(reqs, realtime=True)
     out["poisson"] = st.summary()
     print(json.dumps(out["poisson"]), file=sys.stderr, flush=True)
     if args.saturation:
         reqs2 = requests_from_trace(trace, iters=args.iters)
-        srv2 = Server(budget_bytes=args.budget_mib << 20, precision=args.precision)
+        srv2 = Server(budget_bytes=args.budget_mib << 20, precision=args.precision, **sched)
         out["saturation_batched"] = srv2.run(reqs2, realtime=False).summary()
         print(json.dumps(out["saturation_batched"]), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
