@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_UPDATE = 12          # read log q (4) + read u (4) + write log q' (4)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_step_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 # sources of each workload's dominant kernel: a traffic measurement holds
 # only while they are unchanged
 KERNEL_SOURCES = {
