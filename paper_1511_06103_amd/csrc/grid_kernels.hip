@@ -10,40 +10,48 @@
 namespace mf {
 namespace {
 
-// Initial log q per node: -u - lse(-u) (mode 0) or -log L (mode 1); mode 2
-// only checks the caller's state.  Sets flags[0] on a non-finite input.
 // log q^0 per node (Eq. 6 reading): -u - lse(-u) (mode 0), uniform (mode 1),
-// or the caller's state, checked (mode 2).  LC label slots (the label count
-// rounded up to 2, 4, 8, 16, 21 or 32) hold the node's values in registers:
-// the unaries are read once.
-template <int LC>
-__global__ __launch_bounds__(64) void init_kernel(const float* __restrict__ unary, float* __restrict__ state,
-                                                  int L, int N, int mode, int* __restrict__ flags) {
-  const int n = blockIdx.x * 64 + threadIdx.x;
+// or the caller's state, checked (mode 2).  Sets flags[0] on a non-finite
+// input.  A node's label slots are split over LPN consecutive lanes, LG
+// each (the label count rounded up to LG * LPN), so that a grid of N nodes
+// runs LPN * N threads; the node's max and sum reduce over its lanes with an
+// xor butterfly, whose two operands at each level are the same in both
+// lanes of a pair, so every lane holds the same lse.
+template <int LG, int LPN>
+__global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ unary, float* __restrict__ state,
+                                                   int L, int N, int mode, int* __restrict__ flags) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int n = t / LPN, l0 = (t % LPN) * LG;
   const int b = blockIdx.y;
-  if (n >= N) return;
+  if (n >= N) return;   // the LPN lanes of a node leave together (LPN divides 64)
   const size_t base = (size_t)b * L * N + n;
   bool bad = false;
   if (mode == 0) {
-    float v[LC];
+    float v[LG];
     float mx = -INFINITY;
 #pragma unroll
-    for (int l = 0; l < LC; ++l) {
-      v[l] = l < L ? -unary[base + (size_t)l * N] : -INFINITY;
-      if (l < L) bad |= !isfinite(v[l]);
-      mx = fmaxf(mx, v[l]);
+    for (int j = 0; j < LG; ++j) {
+      const int l = l0 + j;
+      v[j] = l < L ? -unary[base + (size_t)l * N] : -INFINITY;
+      if (l < L) bad |= !isfinite(v[j]);
+      mx = fmaxf(mx, v[j]);
     }
+#pragma unroll
+    for (int off = LPN / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, LPN));
     float se = 0.f;
 #pragma unroll
-    for (int l = 0; l < LC; ++l) se += l < L ? expf(v[l] - mx) : 0.f;
+    for (int j = 0; j < LG; ++j) se += l0 + j < L ? expf(v[j] - mx) : 0.f;
+#pragma unroll
+    for (int off = LPN / 2; off > 0; off >>= 1) se += __shfl_xor(se, off, LPN);
     const float lse = mx + logf(se);
 #pragma unroll
-    for (int l = 0; l < LC; ++l)
-      if (l < L) state[base + (size_t)l * N] = v[l] - lse;
+    for (int j = 0; j < LG; ++j)
+      if (l0 + j < L) state[base + (size_t)(l0 + j) * N] = v[j] - lse;
   } else if (mode == 1) {
     const float u0 = -logf((float)L);
 #pragma unroll
-    for (int l = 0; l < LC; ++l) {
+    for (int j = 0; j < LG; ++j) {
+      const int l = l0 + j;
       if (l < L) {
         bad |= !isfinite(unary[base + (size_t)l * N]);
         state[base + (size_t)l * N] = u0;
@@ -51,7 +59,8 @@ __global__ __launch_bounds__(64) void init_kernel(const float* __restrict__ unar
     }
   } else {
 #pragma unroll
-    for (int l = 0; l < LC; ++l) {
+    for (int j = 0; j < LG; ++j) {
+      const int l = l0 + j;
       if (l < L) {
         bad |= !isfinite(unary[base + (size_t)l * N]);
         bad |= !isfinite(state[base + (size_t)l * N]);
@@ -165,15 +174,20 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
 
 int grid_blocks_per_item(int H, int W) { return (H * W + 255) / 256; }
 
+template <int LG, int LPN>
+void init_lg(const float* unary, float* state, int B, int L, int N, int mode, int* flags, hipStream_t s) {
+  const dim3 grid((unsigned)(((size_t)N * LPN + 255) / 256), B), block(256);
+  hipLaunchKernelGGL((init_kernel<LG, LPN>), grid, block, 0, s, unary, state, L, N, mode, flags);
+}
+
 hipError_t launch_init(const float* unary, float* state, int B, int L, int N, int mode, int* flags,
                        hipStream_t s) {
-  const dim3 grid((N + 63) / 64, B), block(64);
-  if (L <= 2) hipLaunchKernelGGL(init_kernel<2>, grid, block, 0, s, unary, state, L, N, mode, flags);
-  else if (L <= 4) hipLaunchKernelGGL(init_kernel<4>, grid, block, 0, s, unary, state, L, N, mode, flags);
-  else if (L <= 8) hipLaunchKernelGGL(init_kernel<8>, grid, block, 0, s, unary, state, L, N, mode, flags);
-  else if (L <= 16) hipLaunchKernelGGL(init_kernel<16>, grid, block, 0, s, unary, state, L, N, mode, flags);
-  else if (L == 21) hipLaunchKernelGGL(init_kernel<21>, grid, block, 0, s, unary, state, L, N, mode, flags);
-  else hipLaunchKernelGGL(init_kernel<MF_MAX_LABELS>, grid, block, 0, s, unary, state, L, N, mode, flags);
+  if (L <= 2) init_lg<2, 1>(unary, state, B, L, N, mode, flags, s);
+  else if (L <= 4) init_lg<4, 1>(unary, state, B, L, N, mode, flags, s);
+  else if (L <= 8) init_lg<4, 2>(unary, state, B, L, N, mode, flags, s);
+  else if (L <= 16) init_lg<4, 4>(unary, state, B, L, N, mode, flags, s);
+  else if (L <= 24) init_lg<6, 4>(unary, state, B, L, N, mode, flags, s);
+  else init_lg<8, 4>(unary, state, B, L, N, mode, flags, s);
   return hipGetLastError();
 }
 
