@@ -400,6 +400,48 @@ def test_resume_from_state_equals_uninterrupted():
 # the beyond-cache shape at the benchmark launch configuration, sampled
 # ---------------------------------------------------------------------------
 
+def test_largest_problem_init_and_step_sampled():
+    """The largest problem a handle accepts: L * N just below 2^30 (L = 32 on
+    4095 x 8192 nodes, 4.29 GB per array), so the 32-bit byte offsets of the
+    label planes come within 0.03 % of 2^32.  The unaries are drawn on the
+    device from a seeded generator (logits 2 N(0, 1), u = -log_softmax);
+    the initialisation and one step are checked against the oracle at
+    sampled nodes, the last rows and columns included."""
+    from paper_1511_06103_amd import mf
+    H, W, L = 4095, 8192, 32
+    N = H * W
+    assert L * N < 1 << 30 and L * N > (1 << 30) - (1 << 19)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(20)
+    u = 2.0 * torch.randn((1, L, N), generator=gen, device=dev)
+    u = -torch.log_softmax(u, dim=1)
+    th = np.triu(np.random.default_rng(21).uniform(0.0, 2.0, (L, L)), 1)
+    th = (th + th.T).astype(np.float32)
+    s = mf.MeanField(u, "grid8", height=H, width=W, theta=torch.from_numpy(th).to(dev), alpha=0.5)
+    rng = np.random.default_rng(22)
+    ys = np.concatenate([rng.integers(0, H, 300), [0, 0, H - 1, H - 1, H - 1, H - 2, H // 2]])
+    xs = np.concatenate([rng.integers(0, W, 300), [0, W - 1, 0, W - 1, W - 2, W - 1, W - 1]])
+    idx = torch.from_numpy((ys * W + xs).astype(np.int64)).to(dev)
+    torch.cuda.synchronize()
+    ell0_got = s.current_state()[0][:, idx].cpu().numpy().astype(np.float64)
+    s.step(1)
+    got = s.current_state()[0][:, idx].cpu().numpy().astype(np.float64)
+    s.check()
+    worst0 = worst1 = 0.0
+    for k, (y, x) in enumerate(zip(ys, xs)):
+        y0, y1, x0, x1 = max(0, y - 1), min(H, y + 2), max(0, x - 1), min(W, x + 2)
+        nodes = (np.arange(y0, y1)[:, None] * W + np.arange(x0, x1)[None, :]).ravel()
+        uu = u[0][:, torch.from_numpy(nodes).to(dev)].cpu().numpy().astype(np.float64)
+        ell0 = O.init_state(uu)
+        c = (y - y0) * (x1 - x0) + (x - x0)
+        worst0 = max(worst0, cases.max_dq(ell0_got[:, k], ell0[:, c]))
+        sub = O.grid_model(uu, y1 - y0, x1 - x0, 8, theta=th.astype(np.float64))
+        ref = O.prox_step(ell0.astype(np.float32).astype(np.float64), sub, 0.5)
+        worst1 = max(worst1, cases.max_dq(got[:, k], ref[:, c]))
+    s.close()
+    assert worst0 <= 1e-6 and worst1 <= 1e-6, (worst0, worst1)
+
+
 def test_big_grid_one_step_sampled():
     inst = synth.workload_big()
     H, W, L = inst.height, inst.width, inst.n_labels
