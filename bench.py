@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 BYTES_PER_UPDATE = 12          # read log q (4) + read u (4) + write log q' (4)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 # sources of each workload's dominant kernel: a traffic measurement holds
@@ -372,6 +373,18 @@ def main():
                 "algorithmic_bytes_per_launch": algo}
     log(f"{kname} (K={k}): {mean_d * 1e6:.2f} us mean per launch over {args.launches} back-to-back "
         f"launches -> {achieved:.0f} GB/s")
+    if inst.graph == 3:
+        # the K Q product on the BF16 matrix cores: what they issue (N rounded
+        # up to 64, 32 label slots, one product per BF16 plane of q) and the
+        # algorithmic 2 N^2 L, both per launch over the same launch time
+        Np = -(-N // 64) * 64
+        planes = {"f32": 3, "f16": 2, "bf16": 1}[args.precision]
+        issued = 2.0 * B * Np * Np * 32 * planes / mean_d / 1e12
+        algo_fl = 2.0 * B * N * N * L / mean_d / 1e12
+        roofline["mfma"] = {"unit": "TFLOP/s", "peak": MFMA_BF16_PEAK_TFLOPS, "issued": round(issued, 1),
+                            "issued_frac": round(issued / MFMA_BF16_PEAK_TFLOPS, 4),
+                            "algorithmic": round(algo_fl, 1),
+                            "algorithmic_frac": round(algo_fl / MFMA_BF16_PEAK_TFLOPS, 4)}
 
     cpu = None
     if not args.no_cpu:
