@@ -131,13 +131,16 @@ def time_step_launches(solver, torch, launches):
 
 def step_kernel_name(inst, k):
     """The kernel one mf_step(k) launches for this workload (the library's
-    dispatch rule: fused steps for k > 1, Theta S on the matrix cores for a
-    general Theta with 8 < L <= 32)."""
-    L = inst.unary.shape[1]
+    dispatch rule: a grid of at most 1024 nodes and 8 labels whole in one
+    workgroup, up to 256 steps per launch; otherwise fused steps for k > 1,
+    Theta S on the matrix cores for a general Theta with 8 < L <= 32)."""
+    L, N = inst.unary.shape[1], inst.unary.shape[2]
     if inst.graph == 3:      # one step is the MFMA kernel and the per-node kernel, back to back
         return "mf::dense_step_kernel + mf::dense_epilogue_kernel"
     if inst.graph == 2:
         return "mf::csr_step_kernel"
+    if L <= 8 and N <= 1024 and k > 4:   # the fused kernels take at most 4 steps
+        return "mf::whole_grid_kernel"
     if k == 1:
         return "mf::lanes::step_kernel"
     if inst.theta is not None and 8 < L <= 32:

@@ -132,7 +132,9 @@ typedef struct mf_desc {
   float potts_w;           /* POTTS weight (any finite value) */
   int32_t steps_per_launch; /* grids: proximal steps fused into one launch (temporal
                              * blocking); 0 = chosen by the library, 1 = one step per
-                             * launch; clamped to what the tile fits in LDS */
+                             * launch; clamped to what the tile fits in LDS.  With 0, a
+                             * grid of at most 1024 nodes and 8 labels is held whole by
+                             * one workgroup and takes up to 256 steps per launch */
   int32_t rule;            /* mf_rule (MF_RULE_FIXED = 0: the fixed-step proximal update) */
   float rule_gamma1;       /* MOMENTUM / ADAM: decay of the momentum average, in [0, 1) */
   float rule_gamma2;       /* ADAM: decay of the second moment, in [0, 1) */

@@ -21,6 +21,7 @@ struct mf_handle {
   int cur = 0;      // state buffer holding the current iterate
   int iter = 0;     // steps since (re)initialisation
   int k_launch = 1; // steps fused per launch
+  bool whole = false;  // the whole grid in one workgroup, every step of a launch in LDS
   std::string err;
 };
 
@@ -285,6 +286,14 @@ mf_status enqueue_init(mf_handle* h, bool clear_flags) {
   return MF_OK;
 }
 
+// A small grid left to the library's choice runs whole in one workgroup:
+// up to kWholeMaxSteps steps per launch, all in LDS (a 32 x 32 grid is
+// bound by launches otherwise).
+bool choose_whole_grid(const mf_desc& d) {
+  return is_grid(d.graph) && d.rule == MF_RULE_FIXED && d.steps_per_launch <= 0 &&
+         mf::grid_whole_fits(d.n_labels, d.n_nodes);
+}
+
 // Steps per launch: small grids (fewer 64 x 4 tiles than four per compute
 // unit) are bound by launch and memory latency, so several steps are fused:
 // four where Theta S runs on the matrix cores (general Theta, 8 < L <= 32;
@@ -294,6 +303,7 @@ mf_status enqueue_init(mf_handle* h, bool clear_flags) {
 // L = 21 measured fastest at one).
 int choose_steps_per_launch(const mf_desc& d) {
   if (!is_grid(d.graph) || d.rule != MF_RULE_FIXED) return 1;
+  if (choose_whole_grid(d)) return mf::kWholeMaxSteps;
   const int kmax = mf::grid_max_steps_per_launch(d.n_labels, d.compat, d.precision);
   int k = d.steps_per_launch;
   if (k <= 0) {
@@ -382,9 +392,10 @@ mf_status enqueue_steps(mf_handle* h, int n) {
     a.alpha = (float)d.alpha;
     a.potts_w = d.potts_w;
     const int conn = d.graph == MF_GRID4 ? 4 : 8;
-    hipError_t e = ks == 1 ? mf::launch_grid_step_lanes(a, conn, d.compat, d.precision, h->stream)
-                           : mf::launch_grid_multi_step(a, conn, d.compat, d.precision, h->k_launch, ks,
-                                                        h->stream);
+    hipError_t e = h->whole  ? mf::launch_grid_whole(a, conn, d.compat, d.precision, ks, h->stream)
+                   : ks == 1 ? mf::launch_grid_step_lanes(a, conn, d.compat, d.precision, h->stream)
+                             : mf::launch_grid_multi_step(a, conn, d.compat, d.precision, h->k_launch, ks,
+                                                          h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     h->cur ^= 1;
     h->iter += ks;
@@ -425,6 +436,7 @@ mf_status mf_init(const mf_desc* d, mf_handle** out) {
   h->stream = (hipStream_t)d->stream;
   h->ws = layout_for(*d);
   h->k_launch = choose_steps_per_launch(*d);
+  h->whole = choose_whole_grid(*d);
   const mf_status s2 = enqueue_init(h, true);
   if (s2 != MF_OK) {
     g_err = h->err;

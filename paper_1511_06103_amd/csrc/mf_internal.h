@@ -177,6 +177,12 @@ struct WorkspaceLayout {
 hipError_t launch_init(const float* unary, float* state, int B, int L, int N, int mode,
                        int* flags, hipStream_t s);
 // ks <= K sub-steps in one launch of the K-halo kernel; K <= grid_max_steps_per_launch.
+// Small grids (N <= 1024 nodes, L <= kWholeMaxLabels): one workgroup per
+// problem holds the whole grid in LDS and runs ks steps in one launch.
+constexpr int kWholeMaxLabels = 8;
+constexpr int kWholeMaxSteps = 256;   // steps per launch the library picks for them
+bool grid_whole_fits(int L, int N);
+hipError_t launch_grid_whole(const StepArgs& a, int conn, int compat, int precision, int ks, hipStream_t s);
 hipError_t launch_grid_multi_step(const StepArgs& a, int conn, int compat, int precision, int K, int ks,
                                   hipStream_t s);
 int grid_max_steps_per_launch(int L, int compat, int precision);
