@@ -85,3 +85,23 @@ def test_served_results_match_oracle():
                               height=r.height, width=r.width, unary=r.unary, theta=r.theta, alpha=r.alpha, iters=1)
         ref = O.solve(cases.oracle_model(inst), r.alpha, 1)[-1]
         assert np.abs(r.q[0] - np.exp(ref)).max() <= 1e-6
+
+
+def test_full_stream_at_saturation():
+    """The benchmark's stream at its full size: 512 requests (sides 64-512,
+    L in {2, 21}, 100 steps, BF16 messages), all at t = 0.  Every request
+    completes with finite marginals normalised at every node, and eight
+    sampled results equal, bitwise, the same request solved alone (the
+    per-request path that the other tests pin to the oracle; at alpha = 0.5
+    and 100 steps a BF16 run is not comparable with the FP64 oracle
+    element by element, since rounding can switch basins)."""
+    from paper_1511_06103_amd import serving
+    trace = synth.serving_trace(4, 512, 200.0)
+    reqs = serving.requests_from_trace(trace, iters=100)
+    st = serving.Server().run(reqs, realtime=False)
+    assert st.n_done == 512 and st.n_rejected == 0
+    for r in reqs:
+        assert r.status == "done" and np.isfinite(r.q).all()
+        assert np.abs(r.q[0].sum(0) - 1.0).max() <= 1e-5, r.rid
+    for k in np.random.default_rng(5).choice(512, 8, replace=False):
+        np.testing.assert_array_equal(reqs[k].q, serving.solve_alone(reqs[k]))
