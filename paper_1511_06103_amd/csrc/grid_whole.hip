@@ -10,7 +10,12 @@
 //
 // One workgroup per batch item.  LDS holds q of every node twice (this
 // step's and the next), in the message precision; log q and the unaries
-// stay in the node's registers.
+// stay in the node's registers.  A solve can run as one launch: the first
+// launch may take the initialisation (init >= 0, the mf_init_mode) and the
+// last may write q = exp(log q), each with the arithmetic and the order of
+// the separate kernels (the label groups of the initialisation's sums, expf
+// for the write-out), so the results are those of init, steps and
+// write-out launched one by one.
 #include <hip/hip_runtime.h>
 
 #include "mf_internal.h"
@@ -22,7 +27,9 @@ namespace {
 constexpr int kWholeThreads = 1024;
 
 template <int LP, int CONN, int COMPAT, int PREC>
-__global__ __launch_bounds__(kWholeThreads) void whole_grid_kernel(StepArgs a, float one_minus_alpha, int ks) {
+__global__ __launch_bounds__(kWholeThreads) void whole_grid_kernel(StepArgs a, float one_minus_alpha, int ks,
+                                                                   int init, int* __restrict__ flags,
+                                                                   float* __restrict__ q_out) {
   using M = MsgT<PREC>;
   using T = typename M::T;
   __shared__ T qs[2][LP * kWholeThreads];
@@ -42,6 +49,49 @@ __global__ __launch_bounds__(kWholeThreads) void whole_grid_kernel(StepArgs a, f
     const float e_ = a.state_in[at], u_ = a.unary[at];
     ell[l] = v ? e_ : 0.f;
     uu[l] = v ? u_ : 0.f;
+  }
+  if (init >= 0) {
+    // log q^0 as the initialisation kernel forms it: its label groups are
+    // one thread of LG labels (L <= 4) or two of four (L <= 8), each with its
+    // own max and sum, the two combined afterwards
+    constexpr int GL = LP <= 4 ? LP : 4, NG = LP / GL;
+    bool bad = false;
+    if (on) {
+#pragma unroll
+      for (int l = 0; l < LP; ++l) {
+        if (l < L) bad |= !isfinite(uu[l]);
+        if (init == MF_INIT_STATE && l < L) bad |= !isfinite(ell[l]);
+      }
+      if (init == MF_INIT_UNARY) {
+        float v[LP], gm[NG], gs[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          gm[g] = -INFINITY;
+#pragma unroll
+          for (int j = 0; j < GL; ++j) {
+            const int l = g * GL + j;
+            v[l] = l < L ? -uu[l] : -INFINITY;
+            gm[g] = fmaxf(gm[g], v[l]);
+          }
+        }
+        const float mx = NG == 1 ? gm[0] : fmaxf(gm[0], gm[NG - 1]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          gs[g] = 0.f;
+#pragma unroll
+          for (int j = 0; j < GL; ++j) gs[g] += g * GL + j < L ? expf(v[g * GL + j] - mx) : 0.f;
+        }
+        const float se = NG == 1 ? gs[0] : gs[0] + gs[NG - 1];
+        const float lse = mx + logf(se);
+#pragma unroll
+        for (int l = 0; l < LP; ++l) ell[l] = l < L ? v[l] - lse : 0.f;
+      } else if (init == MF_INIT_UNIFORM) {
+        const float u0 = -logf((float)L);
+#pragma unroll
+        for (int l = 0; l < LP; ++l) ell[l] = l < L ? u0 : 0.f;
+      }
+    }
+    if (bad) atomicOr(flags, 1);
   }
   if (COMPAT == MF_COMPAT_GENERAL)
     for (int f = n; f < LP * LP; f += kWholeThreads) {
@@ -133,46 +183,62 @@ __global__ __launch_bounds__(kWholeThreads) void whole_grid_kernel(StepArgs a, f
   }
   if (on) {
 #pragma unroll
-    for (int l = 0; l < LP; ++l)
-      if (l < L) a.state_out[base + (size_t)l * N + n] = ell[l];
+    for (int l = 0; l < LP; ++l) {
+      if (l < L) {
+        a.state_out[base + (size_t)l * N + n] = ell[l];
+        if (q_out) q_out[base + (size_t)l * N + n] = expf(ell[l]);
+      }
+    }
   }
 }
 
+struct WholeExtra {
+  int init;        // mf_init_mode, or -1: the state is already initialised
+  int* flags;
+  float* q_out;    // nullptr: no write-out
+};
+
 template <int LP, int PREC>
-hipError_t whole_lp(const StepArgs& a, int conn, int compat, int ks, hipStream_t s) {
+hipError_t whole_lp(const StepArgs& a, int conn, int compat, int ks, const WholeExtra& x, hipStream_t s) {
   const float om = (float)(1.0 - (double)a.alpha);
   const dim3 grid(a.B), block(kWholeThreads);
   if (conn == 4) {
     if (compat == MF_COMPAT_POTTS)
-      hipLaunchKernelGGL((whole_grid_kernel<LP, 4, MF_COMPAT_POTTS, PREC>), grid, block, 0, s, a, om, ks);
+      hipLaunchKernelGGL((whole_grid_kernel<LP, 4, MF_COMPAT_POTTS, PREC>), grid, block, 0, s, a, om, ks, x.init,
+                         x.flags, x.q_out);
     else
-      hipLaunchKernelGGL((whole_grid_kernel<LP, 4, MF_COMPAT_GENERAL, PREC>), grid, block, 0, s, a, om, ks);
+      hipLaunchKernelGGL((whole_grid_kernel<LP, 4, MF_COMPAT_GENERAL, PREC>), grid, block, 0, s, a, om, ks, x.init,
+                         x.flags, x.q_out);
   } else {
     if (compat == MF_COMPAT_POTTS)
-      hipLaunchKernelGGL((whole_grid_kernel<LP, 8, MF_COMPAT_POTTS, PREC>), grid, block, 0, s, a, om, ks);
+      hipLaunchKernelGGL((whole_grid_kernel<LP, 8, MF_COMPAT_POTTS, PREC>), grid, block, 0, s, a, om, ks, x.init,
+                         x.flags, x.q_out);
     else
-      hipLaunchKernelGGL((whole_grid_kernel<LP, 8, MF_COMPAT_GENERAL, PREC>), grid, block, 0, s, a, om, ks);
+      hipLaunchKernelGGL((whole_grid_kernel<LP, 8, MF_COMPAT_GENERAL, PREC>), grid, block, 0, s, a, om, ks, x.init,
+                         x.flags, x.q_out);
   }
   return hipGetLastError();
 }
 
 template <int PREC>
-hipError_t whole_prec(const StepArgs& a, int conn, int compat, int ks, hipStream_t s) {
-  if (a.L <= 2) return whole_lp<2, PREC>(a, conn, compat, ks, s);
-  if (a.L <= 4) return whole_lp<4, PREC>(a, conn, compat, ks, s);
-  return whole_lp<8, PREC>(a, conn, compat, ks, s);
+hipError_t whole_prec(const StepArgs& a, int conn, int compat, int ks, const WholeExtra& x, hipStream_t s) {
+  if (a.L <= 2) return whole_lp<2, PREC>(a, conn, compat, ks, x, s);
+  if (a.L <= 4) return whole_lp<4, PREC>(a, conn, compat, ks, x, s);
+  return whole_lp<8, PREC>(a, conn, compat, ks, x, s);
 }
 
 }  // namespace
 
 bool grid_whole_fits(int L, int N) { return L >= 1 && L <= kWholeMaxLabels && N >= 1 && N <= kWholeThreads; }
 
-hipError_t launch_grid_whole(const StepArgs& a, int conn, int compat, int precision, int ks, hipStream_t s) {
-  if (!grid_whole_fits(a.L, a.N) || ks < 1) return hipErrorInvalidValue;
+hipError_t launch_grid_whole(const StepArgs& a, int conn, int compat, int precision, int ks, int init, int* flags,
+                             float* q_out, hipStream_t s) {
+  if (!grid_whole_fits(a.L, a.N) || ks < 1 || (init >= 0 && !flags)) return hipErrorInvalidValue;
+  const WholeExtra x{init, flags, q_out};
   switch (precision) {
-    case MF_P_F32: return whole_prec<P_F32>(a, conn, compat, ks, s);
-    case MF_P_BF16MSG: return whole_prec<P_BF16>(a, conn, compat, ks, s);
-    default: return whole_prec<P_F16>(a, conn, compat, ks, s);
+    case MF_P_F32: return whole_prec<P_F32>(a, conn, compat, ks, x, s);
+    case MF_P_BF16MSG: return whole_prec<P_BF16>(a, conn, compat, ks, x, s);
+    default: return whole_prec<P_F16>(a, conn, compat, ks, x, s);
   }
 }
 

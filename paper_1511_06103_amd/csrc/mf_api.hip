@@ -392,7 +392,8 @@ mf_status enqueue_steps(mf_handle* h, int n) {
     a.alpha = (float)d.alpha;
     a.potts_w = d.potts_w;
     const int conn = d.graph == MF_GRID4 ? 4 : 8;
-    hipError_t e = h->whole  ? mf::launch_grid_whole(a, conn, d.compat, d.precision, ks, h->stream)
+    hipError_t e = h->whole  ? mf::launch_grid_whole(a, conn, d.compat, d.precision, ks, -1, nullptr, nullptr,
+                                                      h->stream)
                    : ks == 1 ? mf::launch_grid_step_lanes(a, conn, d.compat, d.precision, h->stream)
                              : mf::launch_grid_multi_step(a, conn, d.compat, d.precision, h->k_launch, ks,
                                                           h->stream);
@@ -457,6 +458,26 @@ mf_status mf_solve(mf_handle* h, int32_t iters, float* q_out) {
   if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
   if (iters < 0) return fail(h, MF_EINVAL, "iters must be >= 0");
   if (((uintptr_t)q_out) & 3u) return fail(h, MF_EINVAL, "q_out must be 4-byte aligned");
+  if (h->whole && iters > 0) {
+    // a small grid held whole by one workgroup: the initialisation, the
+    // steps and the write-out of q in as few launches as the step count
+    // allows, with the arithmetic of the separate kernels
+    const mf_desc& d = h->d;
+    const int conn = d.graph == MF_GRID4 ? 4 : 8;
+    h->cur = 0;
+    h->iter = 0;
+    for (int n = iters, first = 1; n > 0; first = 0) {
+      const int ks = n < h->k_launch ? n : h->k_launch;
+      const mf::StepArgs a = grid_args(h, h->cur);
+      hipError_t e = mf::launch_grid_whole(a, conn, d.compat, d.precision, ks, first ? d.init : -1, flags_ptr(h),
+                                           n == ks ? q_out : nullptr, h->stream);
+      if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+      h->cur ^= 1;
+      h->iter += ks;
+      n -= ks;
+    }
+    return MF_OK;
+  }
   mf_status st = enqueue_init(h, false);
   if (st != MF_OK) return st;
   st = enqueue_steps(h, iters);

@@ -182,7 +182,11 @@ hipError_t launch_init(const float* unary, float* state, int B, int L, int N, in
 constexpr int kWholeMaxLabels = 8;
 constexpr int kWholeMaxSteps = 256;   // steps per launch the library picks for them
 bool grid_whole_fits(int L, int N);
-hipError_t launch_grid_whole(const StepArgs& a, int conn, int compat, int precision, int ks, hipStream_t s);
+// init >= 0: the launch starts with the initialisation of that mf_init_mode
+// (flags[0] set on a non-finite input, as the initialisation kernel does);
+// q_out != nullptr: it ends by writing q = exp(log q) of the last step.
+hipError_t launch_grid_whole(const StepArgs& a, int conn, int compat, int precision, int ks, int init, int* flags,
+                             float* q_out, hipStream_t s);
 hipError_t launch_grid_multi_step(const StepArgs& a, int conn, int compat, int precision, int K, int ks,
                                   hipStream_t s);
 int grid_max_steps_per_launch(int L, int compat, int precision);

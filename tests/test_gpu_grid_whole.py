@@ -100,3 +100,57 @@ def test_whole_grid_long_solve_spans_launches():
     torch.cuda.synchronize()
     ref = O.solve(cases.oracle_model(inst), inst.alpha, 600)[-1]
     assert cases.max_dq(np.log(q.cpu().numpy()[0].astype(np.float64)), ref) <= 1e-5
+
+
+FUSED = [
+    ("L2_unary_50", lambda: synth.grid_potts_normal(52, 32, 2, synth.GRID4, w=1.0), "unary", 50),
+    ("L3_unary_300", lambda: synth.grid_theta_random(53, 20, 30, 3, synth.GRID8), "unary", 300),
+    ("L5_unary_batch2", lambda: synth.grid_theta_random(54, 12, 40, 5, synth.GRID8, batch=2), "unary", 37),
+    ("L8_uniform", lambda: synth.grid_theta_random(55, 31, 32, 8, synth.GRID4), "uniform", 20),
+    ("L6_state", lambda: synth.grid_theta_random(56, 16, 16, 6, synth.GRID8), "state", 12),
+]
+
+
+@pytest.mark.parametrize("name,make,init,iters", FUSED, ids=[f[0] for f in FUSED])
+def test_whole_grid_solve_in_one_launch_equals_separate_kernels(name, make, init, iters):
+    """mf_solve on a small grid runs the initialisation, the steps and the
+    write-out of q inside the whole-grid launches; the state and q equal,
+    bitwise, the initialisation kernel, the steps and the write-out kernel
+    launched one by one (solve(0), step(n), marginals())."""
+    inst = make()
+    if init == "state":
+        start = torch.from_numpy(random_state(np.random.default_rng(8), inst)).to("cuda:0")
+        sts = []
+        for _ in range(2):
+            st = torch.empty((2,) + inst.unary.shape, dtype=torch.float32, device="cuda:0")
+            st[0].copy_(start)
+            sts.append(st)
+    a = cases.gpu_solver(inst, init=init, **({"state": sts[0]} if init == "state" else {}))
+    b = cases.gpu_solver(inst, init=init, **({"state": sts[1]} if init == "state" else {}))
+    qa = torch.empty_like(a.unary)
+    a.solve(iters, qa)
+    b.solve(0)
+    b.step(iters)
+    qb = b.marginals()
+    torch.cuda.synchronize()
+    assert a.iteration == b.iteration == iters
+    assert torch.equal(a.current_state(), b.current_state())
+    assert torch.equal(qa, qb)
+    a.check()
+
+
+def test_whole_grid_solve_reports_a_non_finite_unary():
+    """The initialisation inside the one-launch solve flags a non-finite
+    unary as the initialisation kernel does: the report from creating the
+    handle is taken first (a check clears it), so the second one can only
+    come from the solve."""
+    from paper_1511_06103_amd import mf
+    inst = synth.grid_potts_normal(57, 8, 2, synth.GRID4)
+    inst.unary = inst.unary.copy()
+    inst.unary[0, 1, 5] = np.inf
+    s = cases.gpu_solver(inst)
+    for _ in range(2):
+        with pytest.raises(mf.MFError) as e:
+            s.check()
+        assert e.value.status == mf.MF_ENONFINITE
+        s.solve(4)
