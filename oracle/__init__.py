@@ -12,8 +12,9 @@ arrays of ``paper_1511_06103_amd.synth``, which contains no step of the
 method.  Everything here is plain NumPy in FP64; pure-Python loops appear
 only in the small-case routines (sequential sweep, enumeration).
 
-Every function that has no independent pin is marked "parity unpinned" in
-its docstring.  At present there are none: the pins live in
-``tests/test_oracle_*.py``.
+Every function that has no independent pin would be marked "parity
+unpinned" in its docstring; at present none is.  The pins live in
+``tests/test_oracle_pins.py``; ``tests/test_oracle_mutations.py`` checks
+that they catch mistakes planted in the oracle.
 """
 from .mf import *  # noqa: F401,F403

@@ -21,10 +21,11 @@ All arrays are label-major, ``[L, N]``, float64.
 
 Pins (tests/test_oracle_pins.py): every function here is checked against
 closed forms, brute force, independent library routines or special cases
-that reduce it to another pinned function, with one exception: the
-second-moment average of ``adam_solve`` for gamma2 < 1 (a reading of a
-garbled passage, Sec. 3.5) is checked only through fixed-point
-preservation and normalisation -- parity unpinned for that part.
+that reduce it to another pinned function.  The ADAM reading of Sec. 3.5
+(``adam_solve``) is pinned for gamma2 = 1 by the fixed step and for
+gamma2 < 1 by a scalar recursion worked out by hand for Theta = 0, L = 2.
+tests/test_oracle_mutations.py plants plausible mistakes in these functions
+and checks that a pin fails for each.
 """
 from __future__ import annotations
 

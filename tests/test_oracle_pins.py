@@ -565,3 +565,80 @@ def test_paper_constants_fixture():
     assert inspect.signature(O.momentum_solve).parameters["gamma1"].default == c["momentum_gamma1"]
     assert inspect.signature(O.adam_solve).parameters["gamma2"].default == c["adam_gamma2"]
     assert inspect.signature(O.adam_solve).parameters["eps"].default == c["adam_epsilon"]
+
+
+def _adam_binary_theta_zero_by_hand(du, delta0, d, iters, gamma2, eps, v0):
+    """OURS-ADAM (Eq. 22-23, Sec. 3.5) worked out by hand for Theta = 0 and L = 2.
+
+    With no pairwise term the message is the unary, m = u, at every step, so
+    the momentum average of Sec. 3.4 stays at u.  Write D = log q_0 - log q_1
+    and Du = u_0 - u_1 per node.  The natural gradient g = m + log q, centred
+    over the two labels, is +-(Du + D) / 2: both labels share g^2, hence the
+    second moment and the step.  Normalisation leaves differences alone, so
+    the update of Eq. 15 with eta_t reduces to a scalar recursion per node:
+
+        v_{t+1}   = gamma2 v_t + (1 - gamma2) ((Du + D_t) / 2)^2
+        d_t       = max(sqrt(v_{t+1}) d + eps - 1, 1e-6)
+        eta_t     = 1 / (1 + d_t)
+        D_{t+1}   = (1 - eta_t) D_t - eta_t Du
+    """
+    D = np.array(delta0, dtype=np.float64)
+    v = np.full_like(D, v0)
+    out = [D.copy()]
+    for _ in range(iters):
+        g = 0.5 * (du + D)
+        v = gamma2 * v + (1.0 - gamma2) * g * g
+        dt = np.maximum(np.sqrt(v) * d + eps - 1.0, 1e-6)
+        eta = 1.0 / (1.0 + dt)
+        D = (1.0 - eta) * D - eta * du
+        out.append(D.copy())
+    return out
+
+
+@pytest.mark.parametrize("gamma2", [0.5, 0.999])
+def test_adam_second_moment_binary_theta_zero_recursion(gamma2):
+    """Pins the part of the ADAM reading that the frozen-moment test cannot
+    see: the second-moment average for gamma2 < 1 (its placement, the
+    centring of g, the square, and v being updated before it sets the step).
+    Random starting states keep the natural gradient away from zero, and the
+    unaries and the start are large enough that d_t moves between steps."""
+    rng = np.random.default_rng(77)
+    H, W = 3, 5
+    u = 2.0 * rng.standard_normal((2, H * W))
+    model = O.grid_model(u, H, W, 4, theta=np.zeros((2, 2)))
+    ell0 = _rand_ell(rng, 2, H * W, scale=3.0)
+    d, eps, v0 = 2.5, 1e-3, 0.7
+    traj = O.adam_solve(model, d, 10, gamma1=0.9, gamma2=gamma2, eps=eps, v0=v0, ell0=ell0)
+    ref = _adam_binary_theta_zero_by_hand(u[0] - u[1], ell0[0] - ell0[1], d, 10, gamma2, eps, v0)
+    for e, D in zip(traj, ref):
+        np.testing.assert_allclose(e[0] - e[1], D, rtol=0, atol=1e-12)
+        assert np.abs(np.exp(e).sum(0) - 1.0).max() < 1e-12
+    # the trajectory is not the fixed step at any single eta: the pin sees v move
+    assert np.ptp([np.abs(a - b).max() for a, b in zip(ref[1:], ref[:-1])]) > 1e-3
+
+
+def test_sweep_two_node_by_hand():
+    """One SWEEP (Eq. 8, Sec. 2.2.1) on the two-node Potts example, worked out
+    from the definitions: node 0 sees the old q_1, node 1 the new q_0
+    (Gauss-Seidel), so the result differs from one fully parallel step."""
+    g, model = _two_node()
+    u = np.array(g["unary"])
+    w = g["potts_w"]
+    q = np.array(g["q_test"])
+
+    def softmax_neg(m):
+        e = np.exp(-(m - m.min()))
+        return e / e.sum()
+
+    # Potts with two labels: m_i(0) = u_i(0) + w q_j(1), m_i(1) = u_i(1) + w q_j(0)
+    q0 = softmax_neg(np.array([u[0, 0] + w * q[1, 1], u[1, 0] + w * q[0, 1]]))
+    q1 = softmax_neg(np.array([u[0, 1] + w * q0[1], u[1, 1] + w * q0[0]]))
+    got = np.exp(O.sweep(np.log(q), model, 1))
+    np.testing.assert_allclose(got[:, 0], q0, atol=1e-15)
+    np.testing.assert_allclose(got[:, 1], q1, atol=1e-15)
+    # reversed order: node 1 first, then node 0 with the new q_1
+    r1 = softmax_neg(np.array([u[0, 1] + w * q[1, 0], u[1, 1] + w * q[0, 0]]))
+    r0 = softmax_neg(np.array([u[0, 0] + w * r1[1], u[1, 0] + w * r1[0]]))
+    got = np.exp(O.sweep(np.log(q), model, 1, order=[1, 0]))
+    np.testing.assert_allclose(got[:, 0], r0, atol=1e-15)
+    np.testing.assert_allclose(got[:, 1], r1, atol=1e-15)
