@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define MF_ABI_VERSION 2
+#define MF_ABI_VERSION 3
 #define MF_MAX_LABELS 32   /* largest label count the step kernels accept */
 /* n_labels * n_nodes of one problem must stay below this (2^30): the kernels
    address one problem's [L][N] planes with 32-bit byte offsets.  Larger
@@ -233,16 +233,29 @@ void mf_destroy(mf_handle *h);
  * Valid until the next call on the same handle / thread. */
 const char *mf_last_error(const mf_handle *h);
 
-/* Continuous batching: enqueue n_steps >= 0 proximal steps for each of
- * the count handles hs[0..count) in as few launches as possible (grids
- * with MF_RULE_FIXED only).  Handles with the same label count, connectivity, compatibility
- * kind and precision share a launch; each handle keeps its own sizes,
- * alpha, arrays and iteration counter.  Every handle advances one step per
- * launch, with the same per-tile arithmetic as mf_step at
- * steps_per_launch = 1, so its iterates are bitwise those of solving it
- * alone.  All handles must use the stream of hs[0]; work goes to that
- * stream.  A handle may appear at most once. */
-mf_status mf_step_many(mf_handle *const *hs, int32_t count, int32_t n_steps);
+/* Continuous batching (the parallel update of Eq. 15 applied to many
+ * independent problems at once, Sec. 3.1): enqueue n_steps[i] >= 0
+ * proximal steps for handle hs[i], i < count, in as few launches as
+ * possible (grids with MF_RULE_FIXED only).
+ *
+ * hs:      host array of count handles; a handle may appear at most once.
+ * n_steps: host array of count step counts (NULL is invalid when count > 0).
+ * count:   >= 0; count == 0 enqueues nothing.
+ *
+ * The work runs in rounds: round r advances every handle with
+ * n_steps[i] > r by one step, so problems move at their own pace inside
+ * one call.  Within a round, handles with the same label count (at most 32),
+ * connectivity, compatibility kind and precision share a launch; each keeps
+ * its own sizes, alpha, arrays and iteration counter, with the same
+ * per-tile arithmetic as mf_step at steps_per_launch = 1, so its iterates
+ * are bitwise those of solving it alone that way.  A handle with more than
+ * 32 labels is stepped on its own in its rounds (the kernel of mf_step at
+ * one step per launch).  All handles must use the stream of hs[0]; work goes to
+ * that stream.  Every argument is checked before anything is enqueued
+ * (MF_EINVAL for a NULL array or handle, a negative count, a repeated
+ * handle or a different stream; MF_EUNSUPPORTED for a non-grid graph or
+ * another step rule). */
+mf_status mf_step_many(mf_handle *const *hs, const int32_t *n_steps, int32_t count);
 
 /* Reverse pass of T unrolled steps on a grid (hand-written adjoint of
  * Eq. 15 with Eq. 16, differentiated with respect to the unaries and every
@@ -259,8 +272,9 @@ mf_status mf_step_many(mf_handle *const *hs, int32_t count, int32_t n_steps);
  * grad_theta:  device [L][L], overwritten with dLoss / dTheta summed over
  *   the batch (for POTTS: the gradient with respect to the implied matrix).
  * work: device scratch of mf_backward_workspace_size bytes, 256-aligned.
- * Grids with MF_RULE_FIXED only (MF_EUNSUPPORTED otherwise).  Asynchronous on the stream of h;
- * does not change the state of h. */
+ * Grids with MF_RULE_FIXED, FP32 messages (MF_P_F32) and at most 32 labels
+ * only: MF_EUNSUPPORTED otherwise, and mf_backward_workspace_size returns 0.
+ * Asynchronous on the stream of h; does not change the state of h. */
 size_t mf_backward_workspace_size(const mf_handle *h, int32_t ckpt_every);
 mf_status mf_backward(mf_handle *h, const float *ckpt_states, int32_t T, int32_t ckpt_every,
                       const float *grad_logq_T, float *grad_unary, float *grad_theta,

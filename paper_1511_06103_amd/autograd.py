@@ -52,5 +52,8 @@ def unrolled_mean_field(unary: torch.Tensor, theta: torch.Tensor, *, height: int
 
     unary: [B, L, N] energies; theta: [L, L].  Differentiable in both.
     """
+    if precision != "f32":
+        # the library's adjoint differentiates the step with FP32 messages
+        raise mf.MFError(mf.MF_EUNSUPPORTED, "the adjoint runs with FP32 messages only")
     graph = "grid4" if connectivity == 4 else "grid8"
     return _UnrolledMeanField.apply(unary, theta, graph, height, width, alpha, iters, ckpt_every, precision)

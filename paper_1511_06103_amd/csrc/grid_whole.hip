@@ -1,10 +1,13 @@
 // Small grids in one workgroup: the whole problem (N <= 1024 nodes, L <= 8
 // labels) lives in LDS, one thread per node, and every requested step runs
 // in the same launch, a barrier between steps.  This is the parallel
-// proximal step of Eq. 15 with the fixed step of Eq. 16, exactly as in the
-// tile kernels (same per-node formulas: neighbour sums with a free
+// proximal step of Eq. 15 with the fixed step of Eq. 16 with the same
+// per-node formulas as the tile kernels (neighbour sums with a free
 // boundary, Theta S or the Potts form, the damped step and the per-node
-// log-sum-exp); only the blocking differs.  A launch of the tile kernels
+// log-sum-exp).  The results agree with the tile kernels to FP32 rounding,
+// not bitwise: the next step's q operand here is exp(z - max) / sum, taken
+// from the log-sum-exp, where the single-step tile kernel re-exponentiates
+// the stored log q.  A launch of the tile kernels
 // costs a few microseconds however small the grid, so a 32 x 32 problem is
 // bound by launches, not by the step.
 //

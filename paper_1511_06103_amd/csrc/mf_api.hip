@@ -586,36 +586,52 @@ void mf_destroy(mf_handle* h) { delete h; }
 
 const char* mf_last_error(const mf_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
 
-mf_status mf_step_many(mf_handle* const* hs, int32_t count, int32_t n_steps) {
-  if (count < 0 || n_steps < 0) return fail(nullptr, MF_EINVAL, "count and n_steps must be >= 0");
-  if (count == 0 || n_steps == 0) return MF_OK;
+mf_status mf_step_many(mf_handle* const* hs, const int32_t* n_steps, int32_t count) {
+  if (count < 0) return fail(nullptr, MF_EINVAL, "count must be >= 0");
+  if (count == 0) return MF_OK;
   if (!hs) return fail(nullptr, MF_EINVAL, "hs is NULL");
+  if (!n_steps) return fail(nullptr, MF_EINVAL, "n_steps is NULL");
+  int rounds = 0;
   for (int i = 0; i < count; ++i) {
     if (!hs[i]) return fail(nullptr, MF_EINVAL, "NULL handle in hs");
+    if (n_steps[i] < 0) return fail(hs[i], MF_EINVAL, "n_steps must be >= 0 for every handle");
     if (!is_grid(hs[i]->d.graph)) return fail(hs[i], MF_EUNSUPPORTED, "mf_step_many batches grid problems");
     if (hs[i]->d.rule != MF_RULE_FIXED)
       return fail(hs[i], MF_EUNSUPPORTED, "mf_step_many batches the fixed-step rule");
     if (hs[i]->stream != hs[0]->stream) return fail(hs[i], MF_EINVAL, "handles use different streams");
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[i], MF_EINVAL, "handle listed twice");
+    rounds = std::max(rounds, (int)n_steps[i]);
   }
   const hipStream_t s = hs[0]->stream;
-  std::vector<char> done(count, 0);
-  for (int g = 0; g < count; ++g) {
-    if (done[g]) continue;
-    // the group of handles sharing the kernel instantiation of hs[g]
-    const mf_desc& dg = hs[g]->d;
-    std::vector<mf_handle*> grp;
-    for (int i = g; i < count; ++i) {
-      const mf_desc& di = hs[i]->d;
-      if (!done[i] && di.n_labels == dg.n_labels && di.graph == dg.graph && di.compat == dg.compat &&
-          di.precision == dg.precision) {
-        grp.push_back(hs[i]);
-        done[i] = 1;
+  std::vector<char> done(count);
+  for (int t = 0; t < rounds; ++t) {
+    // the handles that take a step in this round
+    for (int i = 0; i < count; ++i) done[i] = n_steps[i] <= t;
+    for (int g = 0; g < count; ++g) {
+      if (done[g]) continue;
+      const mf_desc& dg = hs[g]->d;
+      if (dg.n_labels > mf::kManyMaxLabels) {
+        // stepped on its own, with the kernel of mf_step at one step per launch
+        done[g] = 1;
+        mf::StepArgs a = grid_args(hs[g], hs[g]->cur);
+        hipError_t e = mf::launch_grid_step_lanes(a, dg.graph == MF_GRID4 ? 4 : 8, dg.compat, dg.precision, s);
+        if (e != hipSuccess) return fail(hs[g], MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+        hs[g]->cur ^= 1;
+        hs[g]->iter += 1;
+        continue;
       }
-    }
-    const int conn = dg.graph == MF_GRID4 ? 4 : 8;
-    for (int t = 0; t < n_steps; ++t) {
+      // the group of handles sharing the kernel instantiation of hs[g]
+      std::vector<mf_handle*> grp;
+      for (int i = g; i < count; ++i) {
+        const mf_desc& di = hs[i]->d;
+        if (!done[i] && di.n_labels == dg.n_labels && di.graph == dg.graph && di.compat == dg.compat &&
+            di.precision == dg.precision) {
+          grp.push_back(hs[i]);
+          done[i] = 1;
+        }
+      }
+      const int conn = dg.graph == MF_GRID4 ? 4 : 8;
       for (size_t c0 = 0; c0 < grp.size(); c0 += mf::kMaxSlots) {
         const size_t c1 = std::min(grp.size(), c0 + (size_t)mf::kMaxSlots);
         mf::ManyArgs m;
@@ -624,23 +640,14 @@ mf_status mf_step_many(mf_handle* const* hs, int32_t count, int32_t n_steps) {
         for (size_t k = c0; k < c1; ++k) {
           mf_handle* h = grp[k];
           const mf_desc& d = h->d;
-          mf::StepArgs& a = m.slot[k - c0];
-          a.unary = d.unary;
-          a.state_in = buf(h, h->cur);
-          a.state_out = buf(h, h->cur ^ 1);
-          a.theta = d.theta;
-          a.B = d.batch;
-          a.L = d.n_labels;
-          a.N = d.n_nodes;
-          a.H = d.height;
-          a.W = d.width;
-          a.alpha = (float)d.alpha;
-          a.potts_w = d.potts_w;
-          m.one_minus_alpha[k - c0] = (float)(1.0 - (double)a.alpha);
-          m.tile_begin[k - c0 + 1] = m.tile_begin[k - c0] + mf::grid_lanes_tiles(d.batch, d.height, d.width, d.n_labels);
+          m.slot[k - c0] = grid_args(h, h->cur);
+          m.one_minus_alpha[k - c0] = (float)(1.0 - (double)m.slot[k - c0].alpha);
+          m.tile_begin[k - c0 + 1] =
+              m.tile_begin[k - c0] + mf::grid_lanes_tiles(d.batch, d.height, d.width, d.n_labels);
         }
         hipError_t e = mf::launch_grid_step_lanes_many(m, dg.n_labels, conn, dg.compat, dg.precision, s);
-        if (e != hipSuccess) return fail(grp[c0], MF_EDEVICE, std::string("batched step launch: ") + hipGetErrorString(e));
+        if (e != hipSuccess)
+          return fail(grp[c0], MF_EDEVICE, std::string("batched step launch: ") + hipGetErrorString(e));
         for (size_t k = c0; k < c1; ++k) {
           grp[k]->cur ^= 1;
           grp[k]->iter += 1;
@@ -652,7 +659,9 @@ mf_status mf_step_many(mf_handle* const* hs, int32_t count, int32_t n_steps) {
 }
 
 size_t mf_backward_workspace_size(const mf_handle* h, int32_t ckpt_every) {
-  if (!h || ckpt_every < 1 || !is_grid(h->d.graph) || h->d.rule != MF_RULE_FIXED) return 0;
+  if (!h || ckpt_every < 1 || !is_grid(h->d.graph) || h->d.rule != MF_RULE_FIXED || h->d.precision != MF_P_F32 ||
+      h->d.n_labels > mf::kManyMaxLabels)
+    return 0;
   const mf_desc& d = h->d;
   const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
   const size_t LL = (size_t)d.n_labels * d.n_labels;
@@ -673,6 +682,10 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
   const mf_desc& d = h->d;
   if (!is_grid(d.graph)) return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for grids");
   if (d.rule != MF_RULE_FIXED) return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for the fixed-step rule");
+  if (d.precision != MF_P_F32)
+    return fail(h, MF_EUNSUPPORTED, "the adjoint differentiates the step with FP32 messages only");
+  if (d.n_labels > mf::kManyMaxLabels)
+    return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for at most 32 labels");
   if (T < 0 || ckpt_every < 1) return fail(h, MF_EINVAL, "need T >= 0 and ckpt_every >= 1");
   if (!ckpt_states || !grad_logq_T || !grad_unary || !grad_theta || !work)
     return fail(h, MF_EINVAL, "NULL argument");

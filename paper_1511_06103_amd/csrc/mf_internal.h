@@ -28,6 +28,7 @@ struct StepArgs {
 
 // Continuous batching: up to kMaxSlots problems advanced by one launch.
 constexpr int kMaxSlots = 48;
+constexpr int kManyMaxLabels = 32;   // label counts the batched kernel is compiled for
 struct ManyArgs {
   StepArgs slot[kMaxSlots];
   float one_minus_alpha[kMaxSlots];

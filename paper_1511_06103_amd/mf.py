@@ -17,8 +17,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")
 
-MF_ABI_VERSION = 2
+MF_ABI_VERSION = 3
 MF_MAX_LABELS = 32
+MF_MAX_LABEL_NODES = 1 << 30   # n_labels * n_nodes of one problem must stay below this
 
 MF_OK, MF_EINVAL, MF_ENONFINITE, MF_EDEVICE, MF_EUNSUPPORTED, MF_ENOWORKSPACE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "MF_OK", -1: "MF_EINVAL", -2: "MF_ENONFINITE", -3: "MF_EDEVICE",
@@ -74,7 +75,8 @@ SIGNATURES = {
     "mf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "mf_dense_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p]),
-    "mf_step_many": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32]),
+    "mf_step_many": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.c_int32]),
     "mf_backward_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int32]),
     "mf_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -151,13 +153,18 @@ def dense_kernel(features: torch.Tensor, stream=None) -> torch.Tensor:
     return K
 
 
-def step_many(solvers, n_steps: int = 1):
-    """Advance every solver by n_steps in shared launches (continuous batching)."""
+def step_many(solvers, n_steps=1):
+    """Advance solver i by n_steps[i] steps (one int: the same for all) in
+    shared launches (continuous batching, mf_step_many)."""
     solvers = list(solvers)
     if not solvers:
         return
+    counts = [int(n_steps)] * len(solvers) if np.isscalar(n_steps) else [int(k) for k in n_steps]
+    if len(counts) != len(solvers):
+        raise ValueError("one step count per solver")
     arr = (ctypes.c_void_p * len(solvers))(*[s._h().value for s in solvers])
-    st = lib().mf_step_many(arr, len(solvers), int(n_steps))
+    cnt = (ctypes.c_int32 * len(solvers))(*counts)
+    st = lib().mf_step_many(arr, cnt, len(solvers))
     if st != MF_OK:
         raise MFError(st, last_error())
 

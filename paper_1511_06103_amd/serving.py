@@ -119,8 +119,8 @@ class Server:
         # admissions per tick (0: all that fit), so that stepping starts while
         # later requests are still uploading
         self.admit_per_tick = int(admit_per_tick)
-        # steps per tick: the active problems advance together by up to this
-        # many steps, never past the one closest to its iteration count
+        # steps per tick: every active problem advances by up to this many
+        # steps, each stopping at its own iteration count
         self.steps_per_tick = max(1, int(steps_per_tick))
         self.used = 0
         self.queue: List[SolveRequest] = []
@@ -132,8 +132,13 @@ class Server:
     def submit(self, req: SolveRequest):
         u, th = req.unary, req.theta
         if (u.ndim != 3 or u.shape[0] != 1 or th.shape != (u.shape[1], u.shape[1])
-                or req.height * req.width != u.shape[2] or not (0.0 < req.alpha <= 1.0) or req.iters < 0):
+                or req.height * req.width != u.shape[2] or not (0.0 < req.alpha <= 1.0) or req.iters < 0
+                or req.connectivity not in (4, 8)):
             return self._reject(req, "malformed request")
+        if not 1 <= req.n_labels <= mf.MF_MAX_LABELS:
+            return self._reject(req, f"label count outside 1..{mf.MF_MAX_LABELS}")
+        if req.n_labels * req.n_nodes >= mf.MF_MAX_LABEL_NODES:
+            return self._reject(req, "n_labels * n_nodes at or above the library's per-problem limit")
         if not (np.isfinite(u).all() and np.isfinite(th).all()):
             return self._reject(req, "non-finite unary or theta")
         if footprint_bytes(req) > self.budget:
@@ -156,8 +161,13 @@ class Server:
             u = torch.from_numpy(req.unary).pin_memory().to(self.device, non_blocking=True)
             th = torch.from_numpy(req.theta).pin_memory().to(self.device, non_blocking=True)
             graph = "grid4" if req.connectivity == 4 else "grid8"
-            s = mf.MeanField(u, graph, height=req.height, width=req.width, theta=th, alpha=req.alpha,
-                             precision=self.precision, steps_per_launch=1)
+            try:
+                s = mf.MeanField(u, graph, height=req.height, width=req.width, theta=th, alpha=req.alpha,
+                                 precision=self.precision, steps_per_launch=1)
+            except mf.MFError as e:
+                # refused by the library: this request alone fails, the budget is not charged
+                self._reject(req, str(e))
+                continue
             self.used += nb
             self.stats.max_used_bytes = max(self.stats.max_used_bytes, self.used)
             req.status, req.t_admit = "running", now
@@ -211,8 +221,9 @@ class Server:
                 i += 1
             self._admit(now)
             if self.active:
-                k = min(self.steps_per_tick, min(s.req.iters - s.solver.iteration for s in self.active))
-                mf.step_many([s.solver for s in self.active], k)
+                # each problem advances at its own pace: up to steps_per_tick, never past its count
+                ks = [min(self.steps_per_tick, s.req.iters - s.solver.iteration) for s in self.active]
+                mf.step_many([s.solver for s in self.active], ks)
                 self.stats.ticks += 1
                 ev = torch.cuda.Event()
                 ev.record()

@@ -221,3 +221,17 @@ def test_step_rules_need_a_grid():
     d = good_desc(graph=mf.CSR, height=0, width=0, csr_row_ptr=rp, csr_col=rp + 4096, csr_nnz=8,
                   rule=mf.RULES["adhoc"])
     assert validate(d) == mf.MF_EUNSUPPORTED
+
+
+def test_step_many_argument_checks_without_a_gpu():
+    """mf_step_many checks its arrays before touching any handle."""
+    L = mf.lib()
+    one = (ctypes.c_int32 * 1)(1)
+    nul = (ctypes.c_void_p * 1)(None)
+    assert L.mf_step_many(None, None, 0) == mf.MF_OK                 # nothing to do
+    assert L.mf_step_many(nul, one, -1) == mf.MF_EINVAL              # negative count
+    assert L.mf_step_many(None, one, 1) == mf.MF_EINVAL              # NULL handle array
+    assert L.mf_step_many(nul, None, 1) == mf.MF_EINVAL              # NULL step counts
+    assert "n_steps" in mf.last_error()
+    assert L.mf_step_many(nul, one, 1) == mf.MF_EINVAL               # NULL handle inside
+    assert "NULL handle" in mf.last_error()

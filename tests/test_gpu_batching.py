@@ -115,3 +115,38 @@ def test_streaming_step_equals_batched_step_bitwise():
         hi = h - 1 if y0 + 5 < 1024 else h
         got = g[:, rows, :][:, lo:hi, :]
         assert cases.max_dq(got.reshape(21, -1), ref[:, lo:hi, :].reshape(21, -1)) <= 1e-6, y0
+
+
+def test_step_many_per_handle_counts_bitwise():
+    """One call advances three problems by 2, 5 and 9 steps (rounds in which
+    the shorter ones drop out); each equals, bitwise, the same problem
+    stepped alone at one step per launch, and the rest of the mix (a
+    different label count and a zero count) moves as asked."""
+    from paper_1511_06103_amd import mf
+    insts = mix()[:5]
+    counts = [2, 5, 9, 0, 4]
+    alone = []
+    for inst, k in zip(insts, counts):
+        s = cases.gpu_solver(inst, steps_per_launch=1)
+        s.step(k)
+        torch.cuda.synchronize()
+        alone.append(s.current_state().clone())
+    solvers = [cases.gpu_solver(inst) for inst in insts]
+    mf.step_many(solvers, counts)
+    torch.cuda.synchronize()
+    for s, a, k in zip(solvers, alone, counts):
+        assert s.iteration == k
+        assert torch.equal(s.current_state(), a)
+
+
+def test_step_many_rejects_bad_counts_before_enqueueing():
+    from paper_1511_06103_amd import mf
+    insts = mix()[:2]
+    solvers = [cases.gpu_solver(inst) for inst in insts]
+    before = [s.current_state().clone() for s in solvers]
+    with pytest.raises(mf.MFError) as e:
+        mf.step_many(solvers, [3, -1])
+    assert e.value.status == mf.MF_EINVAL
+    torch.cuda.synchronize()
+    for s, b in zip(solvers, before):
+        assert s.iteration == 0 and torch.equal(s.current_state(), b)

@@ -67,11 +67,18 @@ def test_bad_requests_are_isolated():
                                      iters=20)
     huge = serving.SolveRequest(102, 0.0, np.zeros((1, 21, 512 * 512), np.float32), reqs[2].theta[:1, :1].repeat(21, 0).repeat(21, 1),
                                 512, 512, iters=20)
+    from paper_1511_06103_amd import mf
+    Lx = mf.MF_MAX_LABELS + 1
+    too_many_labels = serving.SolveRequest(103, 0.0, np.zeros((1, Lx, 64), np.float32),
+                                           np.zeros((Lx, Lx), np.float32), 8, 8, iters=20)
+    bad_conn = serving.SolveRequest(104, 0.0, reqs[3].unary, reqs[3].theta, reqs[3].height, reqs[3].width,
+                                    iters=20, connectivity=6)
+    bad = [bad_nan, bad_shape, huge, too_many_labels, bad_conn]
     budget = max(serving.footprint_bytes(r) for r in reqs) * 3
     srv = serving.Server(budget_bytes=budget)
-    st = srv.run(reqs + [bad_nan, bad_shape, huge], realtime=False)
-    assert st.n_done == 6 and st.n_rejected == 3
-    assert bad_nan.status == bad_shape.status == huge.status == "rejected"
+    st = srv.run(reqs + bad, realtime=False)
+    assert st.n_done == 6 and st.n_rejected == len(bad)
+    assert all(r.status == "rejected" and r.error for r in bad)
     for r in reqs:
         np.testing.assert_array_equal(r.q, serving.solve_alone(r))
 
