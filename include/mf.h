@@ -314,6 +314,32 @@ mf_status mf_lipschitz(mf_handle *h, int32_t iters, const float *v0, const float
 mf_status mf_dense_kernel(const float *features, int32_t n, int32_t dim, uint16_t *K_bf16,
                           void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mf_solve
+ * without a handle and without a caller workspace.  The solve (the
+ * initialisation of d->init, iters steps, q written to q_out when not NULL)
+ * and, when F_out is not NULL, the FP64 free energy of the final state
+ * (F_out[B], device) use the same kernels as mf_init + mf_solve +
+ * mf_free_energy; their scratch (flags, FP64 partial sums, the CSR and
+ * dense staging copies) is a static device array of MF_STATIC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends.
+ *
+ * d: as for mf_init; d->workspace and d->workspace_bytes are ignored.
+ *    d->state [2][B][L][N], the unaries and every other array stay the
+ *    caller's device memory.
+ * flags_out: device int32 or NULL; receives the deferred-error bits of this
+ *    call (bit 0: a non-finite unary or initial state, bit 1: malformed CSR
+ *    arrays), which mf_check would report for a handle.
+ * Returns MF_ENOWORKSPACE (before any HIP call) when the problem's
+ * workspace (mf_workspace_size) exceeds MF_STATIC_SCRATCH_BYTES, and the
+ * codes of mf_init otherwise.  Asynchronous on d->stream: nothing is
+ * allocated, nothing synchronises.  Every call on one GPU shares that GPU's
+ * scratch array and leaves its contents behind (the flags are cleared at
+ * the start of each call): calls that overlap on one GPU, on different
+ * streams or threads, race and give undefined results. */
+#define MF_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+mf_status mf_solve_static(const mf_desc *d, int32_t iters, float *q_out, double *F_out, int32_t *flags_out);
+
 #ifdef __cplusplus
 }
 #endif

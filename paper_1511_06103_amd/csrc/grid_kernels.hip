@@ -74,6 +74,10 @@ __global__ __launch_bounds__(64) void clear_kernel(int* __restrict__ p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
+__global__ __launch_bounds__(64) void copy_flag_kernel(const int* __restrict__ flags, int32_t* __restrict__ out) {
+  if (threadIdx.x == 0) out[0] = flags[0];
+}
+
 __global__ __launch_bounds__(256) void exp_kernel(const float* __restrict__ s, float* __restrict__ q,
                                                   size_t count) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,6 +197,11 @@ hipError_t launch_init(const float* unary, float* state, int B, int L, int N, in
 
 hipError_t launch_clear_flags(int* flags, int n, hipStream_t s) {
   hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, s, flags, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_flags(const int* flags, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(copy_flag_kernel, dim3(1), dim3(64), 0, s, flags, out);
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -405,6 +406,130 @@ mf_status enqueue_steps(mf_handle* h, int n) {
   return MF_OK;
 }
 
+// Re-initialise, run iters steps and write q (mf_solve after its argument checks).
+mf_status solve_impl(mf_handle* h, int iters, float* q_out) {
+  if (h->whole && iters > 0) {
+    // a small grid held whole by one workgroup: the initialisation, the
+    // steps and the write-out of q in as few launches as the step count
+    // allows, with the arithmetic of the separate kernels
+    const mf_desc& d = h->d;
+    const int conn = d.graph == MF_GRID4 ? 4 : 8;
+    h->cur = 0;
+    h->iter = 0;
+    for (int n = iters, first = 1; n > 0; first = 0) {
+      const int ks = n < h->k_launch ? n : h->k_launch;
+      const mf::StepArgs a = grid_args(h, h->cur);
+      hipError_t e = mf::launch_grid_whole(a, conn, d.compat, d.precision, ks, first ? d.init : -1, flags_ptr(h),
+                                           n == ks ? q_out : nullptr, h->stream);
+      if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+      h->cur ^= 1;
+      h->iter += ks;
+      n -= ks;
+    }
+    return MF_OK;
+  }
+  mf_status st = enqueue_init(h, false);
+  if (st != MF_OK) return st;
+  st = enqueue_steps(h, iters);
+  if (st != MF_OK) return st;
+  if (q_out) {
+    const size_t elems = (size_t)h->d.batch * h->d.n_labels * h->d.n_nodes;
+    hipError_t e = mf::launch_exp(buf(h, h->cur), q_out, elems, h->stream);
+    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("exp launch: ") + hipGetErrorString(e));
+  }
+  return MF_OK;
+}
+
+// Enqueue the FP64 free energy of the current state into f_dev[B] (device).
+mf_status enqueue_free_energy(mf_handle* h, double* f_dev) {
+  const mf_desc& d = h->d;
+  mf::FreeEnergyArgs a;
+  a.unary = d.unary;
+  a.state = buf(h, h->cur);
+  a.theta = d.theta;
+  a.B = d.batch;
+  a.L = d.n_labels;
+  a.N = d.n_nodes;
+  a.H = d.height;
+  a.W = d.width;
+  a.potts_w = d.potts_w;
+  a.partials = (double*)((char*)d.workspace + h->ws.partials);
+  a.n_blocks = h->ws.n_blocks;
+  hipError_t e;
+  if (d.graph == MF_CSR) {
+    mf::CsrFreeEnergyArgs c;
+    c.unary = d.unary;
+    c.state = a.state;
+    c.theta = d.theta;
+    c.row_ptr = d.csr_row_ptr;
+    c.col = d.csr_col;
+    c.w = d.csr_w;
+    c.nnz = d.csr_nnz;
+    c.B = d.batch;
+    c.L = d.n_labels;
+    c.N = d.n_nodes;
+    c.potts_w = d.potts_w;
+    c.partials = a.partials;
+    c.n_blocks = a.n_blocks;
+    e = mf::launch_csr_free_energy(c, d.compat, h->stream);
+    if (e == hipSuccess) e = mf::launch_reduce_partials(c.partials, c.n_blocks, c.B, f_dev, h->stream);
+  } else if (d.graph == MF_DENSE) {
+    mf::DenseFreeEnergyArgs c;
+    c.K = d.dense_K;
+    c.unary = d.unary;
+    c.state = a.state;
+    c.theta = d.theta;
+    c.cooc = d.cooc;
+    c.qd = (double*)ws_at(h, h->ws.dqd);
+    c.B = d.batch;
+    c.L = d.n_labels;
+    c.N = d.n_nodes;
+    c.potts_w = d.potts_w;
+    c.partials = a.partials;
+    c.n_blocks = a.n_blocks;
+    e = mf::launch_dense_free_energy(c, d.compat, h->stream);
+    if (e == hipSuccess) e = mf::launch_reduce_partials(c.partials, c.n_blocks, c.B, f_dev, h->stream);
+  } else {
+    e = mf::launch_grid_free_energy(a, d.graph == MF_GRID4 ? 4 : 8, d.compat, f_dev, h->stream);
+  }
+  if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("free-energy launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
+// Scratch of mf_solve_static: the workspace of a solve, in a device array
+// that the library owns (one copy per GPU, held until the process ends), so
+// that the call allocates nothing.  In host code the array's name is only a
+// stand-in: its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[MF_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the current device), or
+// nullptr with *err set.
+void* scratch_address(hipError_t* err) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices)) e = hipErrorInvalidDevice;
+  if (e != hipSuccess) {
+    *err = e;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -458,94 +583,16 @@ mf_status mf_solve(mf_handle* h, int32_t iters, float* q_out) {
   if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
   if (iters < 0) return fail(h, MF_EINVAL, "iters must be >= 0");
   if (((uintptr_t)q_out) & 3u) return fail(h, MF_EINVAL, "q_out must be 4-byte aligned");
-  if (h->whole && iters > 0) {
-    // a small grid held whole by one workgroup: the initialisation, the
-    // steps and the write-out of q in as few launches as the step count
-    // allows, with the arithmetic of the separate kernels
-    const mf_desc& d = h->d;
-    const int conn = d.graph == MF_GRID4 ? 4 : 8;
-    h->cur = 0;
-    h->iter = 0;
-    for (int n = iters, first = 1; n > 0; first = 0) {
-      const int ks = n < h->k_launch ? n : h->k_launch;
-      const mf::StepArgs a = grid_args(h, h->cur);
-      hipError_t e = mf::launch_grid_whole(a, conn, d.compat, d.precision, ks, first ? d.init : -1, flags_ptr(h),
-                                           n == ks ? q_out : nullptr, h->stream);
-      if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
-      h->cur ^= 1;
-      h->iter += ks;
-      n -= ks;
-    }
-    return MF_OK;
-  }
-  mf_status st = enqueue_init(h, false);
-  if (st != MF_OK) return st;
-  st = enqueue_steps(h, iters);
-  if (st != MF_OK) return st;
-  if (q_out) {
-    const size_t elems = (size_t)h->d.batch * h->d.n_labels * h->d.n_nodes;
-    hipError_t e = mf::launch_exp(buf(h, h->cur), q_out, elems, h->stream);
-    if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("exp launch: ") + hipGetErrorString(e));
-  }
-  return MF_OK;
+  return solve_impl(h, iters, q_out);
 }
 
 mf_status mf_free_energy(mf_handle* h, double* F_host) {
   if (!h) return fail(nullptr, MF_EINVAL, "handle is NULL");
   if (!F_host) return fail(h, MF_EINVAL, "F_host is NULL");
-  const mf_desc& d = h->d;
-  mf::FreeEnergyArgs a;
-  a.unary = d.unary;
-  a.state = buf(h, h->cur);
-  a.theta = d.theta;
-  a.B = d.batch;
-  a.L = d.n_labels;
-  a.N = d.n_nodes;
-  a.H = d.height;
-  a.W = d.width;
-  a.potts_w = d.potts_w;
-  a.partials = (double*)((char*)d.workspace + h->ws.partials);
-  a.n_blocks = h->ws.n_blocks;
-  double* f_dev = (double*)((char*)d.workspace + h->ws.f_out);
-  hipError_t e;
-  if (d.graph == MF_CSR) {
-    mf::CsrFreeEnergyArgs c;
-    c.unary = d.unary;
-    c.state = a.state;
-    c.theta = d.theta;
-    c.row_ptr = d.csr_row_ptr;
-    c.col = d.csr_col;
-    c.w = d.csr_w;
-    c.nnz = d.csr_nnz;
-    c.B = d.batch;
-    c.L = d.n_labels;
-    c.N = d.n_nodes;
-    c.potts_w = d.potts_w;
-    c.partials = a.partials;
-    c.n_blocks = a.n_blocks;
-    e = mf::launch_csr_free_energy(c, d.compat, h->stream);
-    if (e == hipSuccess) e = mf::launch_reduce_partials(c.partials, c.n_blocks, c.B, f_dev, h->stream);
-  } else if (d.graph == MF_DENSE) {
-    mf::DenseFreeEnergyArgs c;
-    c.K = d.dense_K;
-    c.unary = d.unary;
-    c.state = a.state;
-    c.theta = d.theta;
-    c.cooc = d.cooc;
-    c.qd = (double*)ws_at(h, h->ws.dqd);
-    c.B = d.batch;
-    c.L = d.n_labels;
-    c.N = d.n_nodes;
-    c.potts_w = d.potts_w;
-    c.partials = a.partials;
-    c.n_blocks = a.n_blocks;
-    e = mf::launch_dense_free_energy(c, d.compat, h->stream);
-    if (e == hipSuccess) e = mf::launch_reduce_partials(c.partials, c.n_blocks, c.B, f_dev, h->stream);
-  } else {
-    e = mf::launch_grid_free_energy(a, d.graph == MF_GRID4 ? 4 : 8, d.compat, f_dev, h->stream);
-  }
-  if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("free-energy launch: ") + hipGetErrorString(e));
-  e = hipMemcpyAsync(F_host, f_dev, sizeof(double) * d.batch, hipMemcpyDeviceToHost, h->stream);
+  double* f_dev = (double*)ws_at(h, h->ws.f_out);
+  const mf_status st = enqueue_free_energy(h, f_dev);
+  if (st != MF_OK) return st;
+  hipError_t e = hipMemcpyAsync(F_host, f_dev, sizeof(double) * h->d.batch, hipMemcpyDeviceToHost, h->stream);
   if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
   return mf_check(h);
 }
@@ -905,6 +952,47 @@ mf_status mf_dense_kernel(const float* features, int32_t n, int32_t dim, uint16_
   if (((uintptr_t)features & 3u) || ((uintptr_t)K_bf16 & 1u)) return fail(nullptr, MF_EINVAL, "misaligned pointer");
   hipError_t e = mf::launch_dense_kernel(features, n, dim, K_bf16, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, MF_EDEVICE, std::string("dense kernel launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
+mf_status mf_solve_static(const mf_desc* d, int32_t iters, float* q_out, double* F_out, int32_t* flags_out) {
+  if (!d) return fail(nullptr, MF_EINVAL, "descriptor is NULL");
+  if (iters < 0) return fail(nullptr, MF_EINVAL, "iters must be >= 0");
+  if (((uintptr_t)q_out & 3u) || ((uintptr_t)F_out & 7u) || ((uintptr_t)flags_out & 3u))
+    return fail(nullptr, MF_EINVAL, "q_out, F_out or flags_out misaligned");
+  if (d->batch < 1 || d->n_nodes < 1 || d->n_labels < 1) return mf_validate(d);
+  // the workspace is the static scratch: check the size before any HIP call
+  mf_desc dd = *d;
+  const size_t need = layout_for(dd).total;
+  if (need > MF_STATIC_SCRATCH_BYTES)
+    return fail(nullptr, MF_ENOWORKSPACE,
+                "problem needs " + std::to_string(need) + " bytes of scratch, above MF_STATIC_SCRATCH_BYTES (" +
+                    std::to_string(MF_STATIC_SCRATCH_BYTES) + ")");
+  dd.workspace = (void*)(uintptr_t)256;   // placeholder for the host-side checks
+  dd.workspace_bytes = MF_STATIC_SCRATCH_BYTES;
+  std::string msg;
+  const mf_status st = check_desc(&dd, &msg);
+  if (st != MF_OK) return fail(nullptr, st, msg);
+  hipError_t e = hipSuccess;
+  void* ws = scratch_address(&e);
+  if (!ws) return fail(nullptr, MF_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+  dd.workspace = ws;
+  mf_handle h;   // on the stack: host memory only, nothing allocated on the device
+  h.d = dd;
+  h.stream = (hipStream_t)dd.stream;
+  h.ws = layout_for(dd);
+  h.k_launch = choose_steps_per_launch(dd);
+  h.whole = choose_whole_grid(dd);
+  // the scratch keeps the previous call's contents: the flags start at zero
+  e = mf::launch_clear_flags(flags_ptr(&h), 64, h.stream);
+  if (e != hipSuccess) return fail(nullptr, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
+  mf_status s2 = solve_impl(&h, iters, q_out);
+  if (s2 == MF_OK && F_out) s2 = enqueue_free_energy(&h, F_out);
+  if (s2 != MF_OK) return fail(nullptr, s2, h.err);
+  if (flags_out) {
+    e = mf::launch_copy_flags(flags_ptr(&h), flags_out, h.stream);
+    if (e != hipSuccess) return fail(nullptr, MF_EDEVICE, std::string("flag copy: ") + hipGetErrorString(e));
+  }
   return MF_OK;
 }
 

@@ -194,6 +194,7 @@ int grid_max_steps_per_launch(int L, int compat, int precision);
 hipError_t launch_grid_free_energy(const FreeEnergyArgs& a, int conn, int compat, double* f_out,
                                    hipStream_t s);
 hipError_t launch_clear_flags(int* flags, int n, hipStream_t s);
+hipError_t launch_copy_flags(const int* flags, int32_t* out, hipStream_t s);   // out[0] = flags[0]
 hipError_t launch_lip_center(const LipArgs& a, const float* v0, hipStream_t s);
 hipError_t launch_lip_hvp(const LipArgs& a, hipStream_t s);
 hipError_t launch_lip_reduce(const LipArgs& a, int n_blocks, int mode, hipStream_t s);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmf.so")
 
 MF_ABI_VERSION = 3
 MF_MAX_LABELS = 32
+MF_STATIC_SCRATCH_BYTES = 64 << 20   # scratch array of mf_solve_static, per GPU
 MF_MAX_LABEL_NODES = 1 << 30   # n_labels * n_nodes of one problem must stay below this
 
 MF_OK, MF_EINVAL, MF_ENONFINITE, MF_EDEVICE, MF_EUNSUPPORTED, MF_ENOWORKSPACE = 0, -1, -2, -3, -4, -5
@@ -86,6 +87,8 @@ SIGNATURES = {
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
     "mf_admissible_alpha": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
+    "mf_solve_static": (ctypes.c_int, [ctypes.POINTER(MFDesc), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
 }
 
 _lib = None
@@ -167,6 +170,21 @@ def step_many(solvers, n_steps=1):
     st = lib().mf_step_many(arr, cnt, len(solvers))
     if st != MF_OK:
         raise MFError(st, last_error())
+
+
+def solve_static(desc: MFDesc, iters: int, q_out: Optional[torch.Tensor] = None,
+                 F_out: Optional[torch.Tensor] = None, flags_out: Optional[torch.Tensor] = None):
+    """mf_solve_static: initialise, run ``iters`` steps, write q into q_out
+    ([B, L, N] float32) and the FP64 free energy into F_out ([B] float64),
+    with the library's static device scratch as the workspace, so that the
+    call allocates nothing.  flags_out (int32 [1]) receives the deferred
+    error bits.  Every array stays the caller's; ``desc`` is an MFDesc
+    (e.g. MeanField.descriptor()).  Asynchronous on desc.stream."""
+    for t, dt, name in ((q_out, torch.float32, "q_out"), (F_out, torch.float64, "F_out"),
+                        (flags_out, torch.int32, "flags_out")):
+        if t is not None:
+            _dev_tensor(t, dt, name, None)
+    _check(lib().mf_solve_static(ctypes.byref(desc), int(iters), _ptr(q_out), _ptr(F_out), _ptr(flags_out)))
 
 
 class MeanField:
@@ -251,6 +269,20 @@ class MeanField:
         h = ctypes.c_void_p()
         _check(L_.mf_init(ctypes.byref(d), ctypes.byref(h)))
         self._handle = h
+
+    def descriptor(self, state: Optional[torch.Tensor] = None) -> MFDesc:
+        """A copy of this problem's mf_desc with no workspace (for
+        solve_static), on ``state`` ([2, B, L, N] float32) if given."""
+        d = MFDesc()
+        ctypes.pointer(d)[0] = self.desc
+        if state is not None:
+            _dev_tensor(state, torch.float32, "state", self.device)
+            if tuple(state.shape) != (2,) + self.shape:
+                raise ValueError("state must be [2, B, L, N]")
+            d.state = _ptr(state)
+        d.workspace = None
+        d.workspace_bytes = 0
+        return d
 
     # -- calls ------------------------------------------------------------
     def _h(self):

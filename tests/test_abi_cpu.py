@@ -235,3 +235,17 @@ def test_step_many_argument_checks_without_a_gpu():
     assert "n_steps" in mf.last_error()
     assert L.mf_step_many(nul, one, 1) == mf.MF_EINVAL               # NULL handle inside
     assert "NULL handle" in mf.last_error()
+
+
+def test_solve_static_checks_before_any_hip_call():
+    """mf_solve_static rejects, on the host, a problem whose workspace
+    exceeds its static scratch, and an invalid descriptor."""
+    L = mf.lib()
+    big = good_desc(graph=mf.DENSE, n_nodes=8192, height=0, width=0)
+    big.dense_K = FAKE + (1 << 36)
+    assert L.mf_solve_static(ctypes.byref(big), 1, None, None, None) == mf.MF_ENOWORKSPACE
+    assert "MF_STATIC_SCRATCH_BYTES" in mf.last_error()
+    bad = good_desc(alpha=0.0)
+    assert L.mf_solve_static(ctypes.byref(bad), 1, None, None, None) == mf.MF_EINVAL
+    assert L.mf_solve_static(None, 1, None, None, None) == mf.MF_EINVAL
+    assert L.mf_solve_static(ctypes.byref(good_desc()), -1, None, None, None) == mf.MF_EINVAL
