@@ -48,7 +48,11 @@ extern "C" {
 #endif
 
 #define MF_ABI_VERSION 3
-#define MF_MAX_LABELS 32   /* largest label count the step kernels accept */
+/* Largest label count: grids with the fixed-step rule take up to 128 labels
+   (above 32 one step per launch, Theta S on the matrix cores); CSR and dense
+   graphs, the other step rules, mf_step_many's shared launches, the adjoint
+   and the power method take up to 32 (MF_EUNSUPPORTED above). */
+#define MF_MAX_LABELS 128
 /* n_labels * n_nodes of one problem must stay below this (2^30): the kernels
    address one problem's [L][N] planes with 32-bit byte offsets.  Larger
    problems are rejected with MF_EUNSUPPORTED. */
@@ -123,7 +127,7 @@ typedef struct mf_desc {
   int32_t batch;           /* B >= 1 problems sharing graph, Theta and alpha */
   int32_t n_nodes;         /* N >= 1 */
   int32_t height, width;   /* grids: height * width == n_nodes; ignored otherwise */
-  int32_t n_labels;        /* 1 <= L <= MF_MAX_LABELS */
+  int32_t n_labels;        /* 1 <= L <= MF_MAX_LABELS (32 off grids, see MF_MAX_LABELS) */
   int32_t graph;           /* mf_graph */
   int32_t compat;          /* mf_compat */
   int32_t precision;       /* mf_precision */

@@ -276,9 +276,9 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
   if (i < N) {
     const size_t base = (size_t)b * L * N;
     const float* st = a.state + base;
-    double S[MF_MAX_LABELS];
+    double S[kSmallLabels];
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) S[l] = 0.0;
+    for (int l = 0; l < kSmallLabels; ++l) S[l] = 0.0;
     long long e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
     e0 = e0 < 0 ? 0 : e0;
     e1 = e1 > a.nnz ? a.nnz : e1;
@@ -287,14 +287,14 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
       if (j < 0 || j >= N) continue;
       const double w = a.w ? (double)a.w[e] : 1.0;
 #pragma unroll
-      for (int l = 0; l < MF_MAX_LABELS; ++l)
+      for (int l = 0; l < kSmallLabels; ++l)
         if (l < L) S[l] += w * exp((double)st[(size_t)l * N + j]);
     }
     double tot = 0.0;
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) tot += S[l];
+    for (int l = 0; l < kSmallLabels; ++l) tot += S[l];
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) {
+    for (int l = 0; l < kSmallLabels; ++l) {
       if (l >= L) continue;
       const double lq = (double)st[(size_t)l * N + i];
       const double q = exp(lq);
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
       } else {
         pm = 0.0;
 #pragma unroll
-        for (int k = 0; k < MF_MAX_LABELS; ++k)
+        for (int k = 0; k < kSmallLabels; ++k)
           if (k < L) pm += (double)a.theta[l * L + k] * S[k];
       }
       f += q * ((double)a.unary[base + (size_t)l * N + i] + lq + 0.5 * pm);

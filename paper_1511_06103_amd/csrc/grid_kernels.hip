@@ -125,9 +125,9 @@ __global__ __launch_bounds__(256) void grid_fe_kernel(FreeEnergyArgs a) {
     const int y = n / W, x = n - (n / W) * W;
     const size_t base = (size_t)b * L * N;
     const float* st = a.state + base;
-    double S[MF_MAX_LABELS];
+    double S[kSmallLabels];
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) S[l] = 0.0;
+    for (int l = 0; l < kSmallLabels; ++l) S[l] = 0.0;
     for (int dy = -1; dy <= 1; ++dy) {
       for (int dx = -1; dx <= 1; ++dx) {
         if (dx == 0 && dy == 0) continue;
@@ -136,15 +136,15 @@ __global__ __launch_bounds__(256) void grid_fe_kernel(FreeEnergyArgs a) {
         if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
         const int j = yy * W + xx;
 #pragma unroll
-        for (int l = 0; l < MF_MAX_LABELS; ++l)
+        for (int l = 0; l < kSmallLabels; ++l)
           if (l < L) S[l] += exp((double)st[(size_t)l * N + j]);
       }
     }
     double tot = 0.0;
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) tot += S[l];
+    for (int l = 0; l < kSmallLabels; ++l) tot += S[l];
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) {
+    for (int l = 0; l < kSmallLabels; ++l) {
       if (l >= L) continue;
       const double lq = (double)st[(size_t)l * N + n];
       const double q = exp(lq);
@@ -154,11 +154,84 @@ __global__ __launch_bounds__(256) void grid_fe_kernel(FreeEnergyArgs a) {
       } else {
         pm = 0.0;
 #pragma unroll
-        for (int k = 0; k < MF_MAX_LABELS; ++k)
+        for (int k = 0; k < kSmallLabels; ++k)
           if (k < L) pm += (double)a.theta[l * L + k] * S[k];
       }
       f += q * ((double)a.unary[base + (size_t)l * N + n] + lq + 0.5 * pm);
     }
+  }
+  const double t = block_sum(f);
+  if (threadIdx.x == 0) a.partials[(size_t)b * a.n_blocks + blockIdx.x] = t;
+}
+
+// The same per-node terms for grids with more labels than grid_fe_kernel
+// holds in registers.  The pairwise half-term is taken in the transposed
+// order, 1/2 sum_l q_l (Theta S)_l = 1/2 sum_k S_k (Theta^T q)_k, over chunks
+// of kSmallLabels labels of S, each chunk of Theta^T q formed from every q_l.
+template <int CONN, int COMPAT>
+__global__ __launch_bounds__(256) void grid_fe_large_kernel(FreeEnergyArgs a) {
+  constexpr int KC = kSmallLabels;
+  const int L = a.L, N = a.N, H = a.H, W = a.W;
+  const int b = blockIdx.y;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  double f = 0.0;
+  if (n < N) {
+    const int y = n / W, x = n - (n / W) * W;
+    const size_t base = (size_t)b * L * N;
+    const float* st = a.state + base;
+    int nbr[8];
+    int nn = 0;
+    for (int dy = -1; dy <= 1; ++dy) {
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (dx == 0 && dy == 0) continue;
+        if (CONN == 4 && dx != 0 && dy != 0) continue;
+        const int yy = y + dy, xx = x + dx;
+        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+        nbr[nn++] = yy * W + xx;
+      }
+    }
+    double qtot = 0.0;
+    for (int l = 0; l < L; ++l) {
+      const double lq = (double)st[(size_t)l * N + n];
+      const double q = exp(lq);
+      qtot += q;
+      f += q * ((double)a.unary[base + (size_t)l * N + n] + lq);
+    }
+    double pair = 0.0;
+    for (int k0 = 0; k0 < L; k0 += KC) {
+      double S[KC];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) S[k] = 0.0;
+      for (int t = 0; t < nn; ++t) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+          if (k0 + k < L) S[k] += exp((double)st[(size_t)(k0 + k) * N + nbr[t]]);
+      }
+      if (COMPAT == MF_COMPAT_POTTS) {
+        // Theta = w (1 1^T - I): sum_k S_k (w qtot - w q_k)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          if (k0 + k < L) {
+            const double qk = exp((double)st[(size_t)(k0 + k) * N + n]);
+            pair += S[k] * (double)a.potts_w * (qtot - qk);
+          }
+        }
+      } else {
+        double r[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) r[k] = 0.0;
+        for (int l = 0; l < L; ++l) {
+          const double q = exp((double)st[(size_t)l * N + n]);
+          const float* th = a.theta + (size_t)l * L + k0;
+#pragma unroll
+          for (int k = 0; k < KC; ++k)
+            if (k0 + k < L) r[k] += (double)th[k] * q;
+        }
+#pragma unroll
+        for (int k = 0; k < KC; ++k) pair += S[k] * r[k];
+      }
+    }
+    f += 0.5 * pair;
   }
   const double t = block_sum(f);
   if (threadIdx.x == 0) a.partials[(size_t)b * a.n_blocks + blockIdx.x] = t;
@@ -191,7 +264,9 @@ hipError_t launch_init(const float* unary, float* state, int B, int L, int N, in
   else if (L <= 8) init_lg<4, 2>(unary, state, B, L, N, mode, flags, s);
   else if (L <= 16) init_lg<4, 4>(unary, state, B, L, N, mode, flags, s);
   else if (L <= 24) init_lg<6, 4>(unary, state, B, L, N, mode, flags, s);
-  else init_lg<8, 4>(unary, state, B, L, N, mode, flags, s);
+  else if (L <= 32) init_lg<8, 4>(unary, state, B, L, N, mode, flags, s);
+  else if (L <= 64) init_lg<8, 8>(unary, state, B, L, N, mode, flags, s);
+  else init_lg<16, 8>(unary, state, B, L, N, mode, flags, s);
   return hipGetLastError();
 }
 
@@ -220,7 +295,15 @@ hipError_t launch_exp(const float* state, float* q, size_t count, hipStream_t s)
 hipError_t launch_grid_free_energy(const FreeEnergyArgs& a, int conn, int compat, double* f_out,
                                    hipStream_t s) {
   dim3 grid(a.n_blocks, a.B);
-  if (conn == 4) {
+  if (a.L > kSmallLabels) {
+    if (conn == 4) {
+      if (compat == MF_COMPAT_POTTS) hipLaunchKernelGGL((grid_fe_large_kernel<4, MF_COMPAT_POTTS>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((grid_fe_large_kernel<4, MF_COMPAT_GENERAL>), grid, dim3(256), 0, s, a);
+    } else {
+      if (compat == MF_COMPAT_POTTS) hipLaunchKernelGGL((grid_fe_large_kernel<8, MF_COMPAT_POTTS>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((grid_fe_large_kernel<8, MF_COMPAT_GENERAL>), grid, dim3(256), 0, s, a);
+    }
+  } else if (conn == 4) {
     if (compat == MF_COMPAT_POTTS) hipLaunchKernelGGL((grid_fe_kernel<4, MF_COMPAT_POTTS>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((grid_fe_kernel<4, MF_COMPAT_GENERAL>), grid, dim3(256), 0, s, a);
   } else {

@@ -8,6 +8,7 @@ namespace mf {
 int grid_lanes_tiles(int B, int H, int W, int L) { return lanes::tiles(B, H, W, L); }
 
 hipError_t launch_grid_step_lanes(const StepArgs& a, int conn, int compat, int prec, hipStream_t s) {
+  if (a.L > kSmallLabels) return launch_grid_step_large(a, conn, compat, prec, s);
   switch (prec) {
     case MF_P_F32: return lanes::launch_f32(a, conn, compat, s);
     case MF_P_BF16MSG: return lanes::launch_bf16(a, conn, compat, s);

@@ -47,16 +47,16 @@ __device__ inline void block_sum_store(double (&x)[NV], double* red, double* par
 
 // Centre, shift and accumulate for one node: h is H v at the node (FP32),
 // vo the node's v.  Writes w and adds to the three partial sums.
-__device__ inline void finish_node(float (&h)[MF_MAX_LABELS], const float (&vo)[MF_MAX_LABELS], int L,
+__device__ inline void finish_node(float (&h)[kSmallLabels], const float (&vo)[kSmallLabels], int L,
                                    unsigned N, unsigned n, float shift, float* __restrict__ w, double& ww,
                                    double& vw, double& vv) {
   float mean = 0.f;
 #pragma unroll
-  for (int l = 0; l < MF_MAX_LABELS; ++l)
+  for (int l = 0; l < kSmallLabels; ++l)
     if (l < L) mean += h[l];
   mean /= (float)L;
 #pragma unroll
-  for (int l = 0; l < MF_MAX_LABELS; ++l) {
+  for (int l = 0; l < kSmallLabels; ++l) {
     if (l < L) {
       const float wl = (h[l] - mean) + shift * vo[l];
       w[(unsigned)l * N + n] = wl;
@@ -68,22 +68,22 @@ __device__ inline void finish_node(float (&h)[MF_MAX_LABELS], const float (&vo)[
   }
 }
 
-__device__ inline void compat_product(const LipArgs& a, const float (&S)[MF_MAX_LABELS], float (&h)[MF_MAX_LABELS]) {
+__device__ inline void compat_product(const LipArgs& a, const float (&S)[kSmallLabels], float (&h)[kSmallLabels]) {
   const int L = a.L;
   if (a.compat == MF_COMPAT_POTTS) {
     float tot = 0.f;
 #pragma unroll
-    for (int k = 0; k < MF_MAX_LABELS; ++k)
+    for (int k = 0; k < kSmallLabels; ++k)
       if (k < L) tot += S[k];
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) h[l] = l < L ? a.potts_w * (tot - S[l]) : 0.f;
+    for (int l = 0; l < kSmallLabels; ++l) h[l] = l < L ? a.potts_w * (tot - S[l]) : 0.f;
   } else {
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) {
+    for (int l = 0; l < kSmallLabels; ++l) {
       float acc = 0.f;
       if (l < L) {
 #pragma unroll
-        for (int k = 0; k < MF_MAX_LABELS; ++k)
+        for (int k = 0; k < kSmallLabels; ++k)
           if (k < L) acc = fmaf(a.theta[l * L + k], S[k], acc);
       }
       h[l] = acc;
@@ -232,8 +232,8 @@ __global__ __launch_bounds__(kSparseThreads) void lip_hvp_csr_kernel(LipArgs a) 
 // C (T - v_i) / N with T the (scaled) column sums of v, and the per-label
 // column sums of w for the next iteration.
 __global__ __launch_bounds__(kLipThreads) void lip_hvp_dense_kernel(LipArgs a) {
-  __shared__ double red[kLipWaves * (3 + MF_MAX_LABELS)];
-  __shared__ float rows_w[kLipWaves][MF_MAX_LABELS];
+  __shared__ double red[kLipWaves * (3 + kSmallLabels)];
+  __shared__ float rows_w[kLipWaves][kSmallLabels];
   const unsigned N = (unsigned)a.N;
   const int L = a.L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -241,40 +241,40 @@ __global__ __launch_bounds__(kLipThreads) void lip_hvp_dense_kernel(LipArgs a) {
   const float scale = (float)a.sc[0];
   const float shift = (float)a.sc[1];
   double x[3] = {0.0, 0.0, 0.0};
-  float S[MF_MAX_LABELS];
+  float S[kSmallLabels];
 #pragma unroll
-  for (int l = 0; l < MF_MAX_LABELS; ++l) S[l] = 0.f;
+  for (int l = 0; l < kSmallLabels; ++l) S[l] = 0.f;
   if (i < N) {
     const uint16_t* Ki = a.K + (size_t)i * N;
     for (unsigned j = lane; j < N; j += 64) {
       const float k = __uint_as_float((unsigned)Ki[j] << 16);
 #pragma unroll
-      for (int l = 0; l < MF_MAX_LABELS; ++l)
+      for (int l = 0; l < kSmallLabels; ++l)
         if (l < L) S[l] = fmaf(k, a.v[(unsigned)l * N + j], S[l]);
     }
   }
 #pragma unroll
-  for (int l = 0; l < MF_MAX_LABELS; ++l) {
+  for (int l = 0; l < kSmallLabels; ++l) {
     float s = S[l];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     S[l] = s * scale;
   }
-  float wrow[MF_MAX_LABELS];
+  float wrow[kSmallLabels];
 #pragma unroll
-  for (int l = 0; l < MF_MAX_LABELS; ++l) wrow[l] = 0.f;
+  for (int l = 0; l < kSmallLabels; ++l) wrow[l] = 0.f;
   if (i < N && lane == 0) {
-    float vo[MF_MAX_LABELS], h[MF_MAX_LABELS];
+    float vo[kSmallLabels], h[kSmallLabels];
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) vo[l] = l < L ? scale * a.v[(unsigned)l * N + i] : 0.f;
+    for (int l = 0; l < kSmallLabels; ++l) vo[l] = l < L ? scale * a.v[(unsigned)l * N + i] : 0.f;
     compat_product(a, S, h);
     if (a.cooc) {
       // C (T - v_i) / N in FP64 (T is kept in FP64 by the reduction)
 #pragma unroll
-      for (int l = 0; l < MF_MAX_LABELS; ++l) {
+      for (int l = 0; l < kSmallLabels; ++l) {
         if (l < L) {
           double c = 0.0;
 #pragma unroll
-          for (int k = 0; k < MF_MAX_LABELS; ++k)
+          for (int k = 0; k < kSmallLabels; ++k)
             if (k < L) c += (double)a.cooc[l * L + k] * (a.sc[2 + k] - (double)vo[k]);
           h[l] += (float)(c / (double)N);
         }
@@ -282,18 +282,18 @@ __global__ __launch_bounds__(kLipThreads) void lip_hvp_dense_kernel(LipArgs a) {
     }
     finish_node(h, vo, L, N, i, shift, a.w, x[0], x[1], x[2]);
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) wrow[l] = h[l];
+    for (int l = 0; l < kSmallLabels; ++l) wrow[l] = h[l];
   }
   // per-label column sums of w over the block's rows (lane 0 of each wave holds its row)
   if (lane == 0) {
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) rows_w[wave][l] = wrow[l];
+    for (int l = 0; l < kSmallLabels; ++l) rows_w[wave][l] = wrow[l];
   }
   double xs[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) xs[t] = lane == 0 ? x[t] : 0.0;
   block_sum_store<3>(xs, red, a.part + (size_t)blockIdx.x * a.np);
-  if (threadIdx.x < MF_MAX_LABELS) {
+  if (threadIdx.x < kSmallLabels) {
     double s = 0.0;
     for (int w = 0; w < kLipWaves; ++w) s += (double)rows_w[w][threadIdx.x];
     a.part[(size_t)blockIdx.x * a.np + 3 + threadIdx.x] = s;
@@ -303,21 +303,21 @@ __global__ __launch_bounds__(kLipThreads) void lip_hvp_dense_kernel(LipArgs a) {
 // v = v0 - mean over labels (per node) into a.w, with the partial sums of
 // v.v (slot 2) and, for the co-occurrence term, of v per label.
 __global__ __launch_bounds__(kLipThreads) void lip_center_kernel(LipArgs a, const float* __restrict__ v0) {
-  __shared__ double red[kLipWaves * (3 + MF_MAX_LABELS)];
+  __shared__ double red[kLipWaves * (3 + kSmallLabels)];
   const unsigned N = (unsigned)a.N;
   const int L = a.L;
   const unsigned n = blockIdx.x * kLipThreads + threadIdx.x;
-  double x[3 + MF_MAX_LABELS];
+  double x[3 + kSmallLabels];
 #pragma unroll
-  for (int t = 0; t < 3 + MF_MAX_LABELS; ++t) x[t] = 0.0;
+  for (int t = 0; t < 3 + kSmallLabels; ++t) x[t] = 0.0;
   if (n < N) {
     float mean = 0.f;
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l)
+    for (int l = 0; l < kSmallLabels; ++l)
       if (l < L) mean += v0[(unsigned)l * N + n];
     mean /= (float)L;
 #pragma unroll
-    for (int l = 0; l < MF_MAX_LABELS; ++l) {
+    for (int l = 0; l < kSmallLabels; ++l) {
       if (l < L) {
         const float c = v0[(unsigned)l * N + n] - mean;
         a.w[(unsigned)l * N + n] = c;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kLipThreads) void lip_center_kernel(LipArgs a, cons
     }
   }
   if (a.np > 3) {
-    block_sum_store<3 + MF_MAX_LABELS>(x, red, a.part + (size_t)blockIdx.x * a.np);
+    block_sum_store<3 + kSmallLabels>(x, red, a.part + (size_t)blockIdx.x * a.np);
   } else {
     double y[3] = {x[0], x[1], x[2]};
     block_sum_store<3>(y, red, a.part + (size_t)blockIdx.x * a.np);
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kLipThreads) void lip_center_kernel(LipArgs a, cons
 // res: [0] rho, [1] lam, [2] run-1 stopped, [3] run-2 stopped.
 __global__ __launch_bounds__(kLipThreads) void lip_reduce_kernel(LipArgs a, int n_blocks, int mode) {
   __shared__ double red[kLipThreads];
-  __shared__ double tot[3 + MF_MAX_LABELS];
+  __shared__ double tot[3 + kSmallLabels];
   const int tid = threadIdx.x;
   for (int c = 0; c < a.np; ++c) {
     double s = 0.0;

@@ -125,6 +125,10 @@ mf_status check_desc(const mf_desc* d, std::string* msg) {
     *msg = "n_labels above MF_MAX_LABELS";
     return MF_EUNSUPPORTED;
   }
+  if (d->n_labels > mf::kSmallLabels && (!is_grid(d->graph) || d->rule != MF_RULE_FIXED)) {
+    *msg = "more than 32 labels are implemented for grids with the fixed-step rule";
+    return MF_EUNSUPPORTED;
+  }
   if (d->rule != MF_RULE_FIXED) {
     if (!is_grid(d->graph)) {
       *msg = "step rules other than MF_RULE_FIXED are implemented for grids";
@@ -303,7 +307,7 @@ bool choose_whole_grid(const mf_desc& d) {
 // stream HBM at one step per launch (16 x 128 x 128 and 2048 x 2048 at
 // L = 21 measured fastest at one).
 int choose_steps_per_launch(const mf_desc& d) {
-  if (!is_grid(d.graph) || d.rule != MF_RULE_FIXED) return 1;
+  if (!is_grid(d.graph) || d.rule != MF_RULE_FIXED || d.n_labels > mf::kSmallLabels) return 1;
   if (choose_whole_grid(d)) return mf::kWholeMaxSteps;
   const int kmax = mf::grid_max_steps_per_launch(d.n_labels, d.compat, d.precision);
   int k = d.steps_per_launch;
@@ -658,7 +662,7 @@ mf_status mf_step_many(mf_handle* const* hs, const int32_t* n_steps, int32_t cou
     for (int g = 0; g < count; ++g) {
       if (done[g]) continue;
       const mf_desc& dg = hs[g]->d;
-      if (dg.n_labels > mf::kManyMaxLabels) {
+      if (dg.n_labels > mf::kSmallLabels) {
         // stepped on its own, with the kernel of mf_step at one step per launch
         done[g] = 1;
         mf::StepArgs a = grid_args(hs[g], hs[g]->cur);
@@ -707,7 +711,7 @@ mf_status mf_step_many(mf_handle* const* hs, const int32_t* n_steps, int32_t cou
 
 size_t mf_backward_workspace_size(const mf_handle* h, int32_t ckpt_every) {
   if (!h || ckpt_every < 1 || !is_grid(h->d.graph) || h->d.rule != MF_RULE_FIXED || h->d.precision != MF_P_F32 ||
-      h->d.n_labels > mf::kManyMaxLabels)
+      h->d.n_labels > mf::kSmallLabels)
     return 0;
   const mf_desc& d = h->d;
   const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
@@ -731,7 +735,7 @@ mf_status mf_backward(mf_handle* h, const float* ckpt_states, int32_t T, int32_t
   if (d.rule != MF_RULE_FIXED) return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for the fixed-step rule");
   if (d.precision != MF_P_F32)
     return fail(h, MF_EUNSUPPORTED, "the adjoint differentiates the step with FP32 messages only");
-  if (d.n_labels > mf::kManyMaxLabels)
+  if (d.n_labels > mf::kSmallLabels)
     return fail(h, MF_EUNSUPPORTED, "the adjoint is implemented for at most 32 labels");
   if (T < 0 || ckpt_every < 1) return fail(h, MF_EINVAL, "need T >= 0 and ckpt_every >= 1");
   if (!ckpt_states || !grad_logq_T || !grad_unary || !grad_theta || !work)
@@ -844,7 +848,7 @@ struct LipLayout {
 LipLayout lip_layout(const mf_desc& d) {
   LipLayout l;
   const size_t LN = (size_t)d.n_labels * d.n_nodes;
-  l.np = d.graph == MF_DENSE ? 3 + MF_MAX_LABELS : 3;
+  l.np = d.graph == MF_DENSE ? 3 + mf::kSmallLabels : 3;
   const int hb = mf::lip_blocks(d.graph, d.n_nodes, d.height, d.width);
   const int cb = (d.n_nodes + 255) / 256;
   l.blocks = hb > cb ? hb : cb;
@@ -854,7 +858,7 @@ LipLayout lip_layout(const mf_desc& d) {
   l.b = off;
   off += align256(sizeof(float) * LN);
   l.sc = off;
-  off += align256(sizeof(double) * (2 + MF_MAX_LABELS));
+  off += align256(sizeof(double) * (2 + mf::kSmallLabels));
   l.res = off;
   off += align256(sizeof(double) * 4);
   l.part = off;
@@ -884,6 +888,8 @@ mf_status mf_lipschitz(mf_handle* h, int32_t iters, const float* v0, const float
   if ((uintptr_t)work & 255u) return fail(h, MF_EINVAL, "work must be 256-byte aligned");
   const LipLayout lay = lip_layout(d);
   if (work_bytes < lay.total) return fail(h, MF_ENOWORKSPACE, "work smaller than mf_lipschitz_workspace_size");
+  if (d.n_labels > mf::kSmallLabels)
+    return fail(h, MF_EUNSUPPORTED, "the power method is implemented for at most 32 labels");
   if (d.n_labels == 1) {   // the tangent space is {0}
     *lambda_max = 0.0;
     *rho = 0.0;

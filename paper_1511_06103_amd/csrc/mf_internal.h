@@ -28,7 +28,11 @@ struct StepArgs {
 
 // Continuous batching: up to kMaxSlots problems advanced by one launch.
 constexpr int kMaxSlots = 48;
-constexpr int kManyMaxLabels = 32;   // label counts the batched kernel is compiled for
+// Label counts of the per-thread kernels (the batched, fused and rule grid
+// kernels, CSR, dense, adjoint, Lipschitz, the small free energy); grids with
+// more labels (up to MF_MAX_LABELS) take one step per launch with Theta S on
+// the matrix cores (grid_large.hip).
+constexpr int kSmallLabels = 32;
 struct ManyArgs {
   StepArgs slot[kMaxSlots];
   float one_minus_alpha[kMaxSlots];
@@ -109,10 +113,10 @@ struct RuleArgs {
 struct LipArgs {
   const float* v;          // [L][N] current iterate, before its scale
   float* w;                // [L][N] output
-  double* sc;              // [2 + MF_MAX_LABELS]: scale of v, shift, column sums T of scaled v
+  double* sc;              // [2 + kSmallLabels]: scale of v, shift, column sums T of scaled v
   double* res;             // [4]: rho, lambda, run-1 stopped, run-2 stopped
   double* part;            // [blocks][np] FP64 partial sums
-  int np;                  // 3, or 3 + MF_MAX_LABELS on a dense graph (column sums)
+  int np;                  // 3, or 3 + kSmallLabels on a dense graph (column sums)
   int graph, compat, L, N, H, W;
   float potts_w;
   const float* theta;      // [L][L] (general)
@@ -236,7 +240,10 @@ hipError_t launch_copy_f32(const float* src, float* dst, size_t n, hipStream_t s
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t s);
 
 int grid_lanes_tiles(int B, int H, int W, int L);
+// One step per launch; grids with more than kSmallLabels labels go to the
+// matrix-core kernel of grid_large.hip.
 hipError_t launch_grid_step_lanes(const StepArgs& a, int conn, int compat, int prec, hipStream_t s);
+hipError_t launch_grid_step_large(const StepArgs& a, int conn, int compat, int prec, hipStream_t s);
 hipError_t launch_grid_step_lanes_many(const ManyArgs& m, int L, int conn, int compat, int prec, hipStream_t s);
 
 int grid_blocks_per_item(int H, int W);

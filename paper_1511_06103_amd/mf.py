@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")
 
 MF_ABI_VERSION = 3
-MF_MAX_LABELS = 32
+MF_MAX_LABELS = 128   # grids with the fixed-step rule; 32 elsewhere
+MF_SMALL_LABELS = 32
 MF_STATIC_SCRATCH_BYTES = 64 << 20   # scratch array of mf_solve_static, per GPU
 MF_MAX_LABEL_NODES = 1 << 30   # n_labels * n_nodes of one problem must stay below this
 

@@ -164,6 +164,14 @@ def workload_big():
     return grid_theta_random(20, 2048, 2048, 21, GRID8, 1, 0.5, 20, name="grid2048_L21_theta")
 
 
+def workload_large_labels(side=512, n_labels=128):
+    """512 x 512, 8-connected, L = 128, the 256 x 256 recipe (random Theta
+    U[0,2], -log_softmax unaries, alpha 0.5) with many labels: Theta S is a
+    real dense contraction; 20 iterations.  Its three arrays of a step
+    (400 MB) exceed the 256 MB last-level cache."""
+    return grid_theta_random(30, side, side, n_labels, GRID8, 1, 0.5, 20, name=f"grid{side}_L{n_labels}_theta")
+
+
 def workload_c5():
     """Batch of 16 grids 128 x 128, 8-connected, L = 21, T = 10 unrolled steps."""
     return grid_theta_random(5, 128, 128, 21, GRID8, 16, 0.5, 10, name="batch16_grid128_L21")

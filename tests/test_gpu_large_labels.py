@@ -1,0 +1,194 @@
+"""Grids with many labels (32 < L <= 128): Theta S on the matrix cores
+(grid_large.hip), against the FP64 oracle.
+
+* one step from an identical FP32 state: 1e-6 with FP32 messages, 2e-3
+  with BF16 and 2e-4 with FP16 messages (the bars of the other grid
+  kernels), at L = 48, 64, 100 and 128, 4- and 8-connected, general Theta
+  and Potts, ragged widths that span several 64-node tiles;
+* 10 steps end to end from q^0 = softmax(-u): FP32 within 1e-5; the 16-bit
+  modes within the one-step bars, measured against the oracle run with q
+  rounded the same way where the rounding is compounded;
+* the initialisation and the FP64 free energy (1e-10 relative);
+* the 512 x 512, L = 128 benchmark shape at one step, on sampled rows;
+* continuous batching: a many-label handle stepped by mf_step_many equals
+  the same handle stepped alone.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import cases  # noqa: E402
+import oracle as O  # noqa: E402
+from paper_1511_06103_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ONE_STEP = {"f32": 1e-6, "bf16": 2e-3, "f16": 2e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu_state(s):
+    torch.cuda.synchronize()
+    return s.current_state().detach().cpu().numpy().astype(np.float64)
+
+
+def solver_from_state(inst, ell_fp32, **kw):
+    B, L, N = inst.unary.shape
+    st = torch.empty((2, B, L, N), dtype=torch.float32, device="cuda:0")
+    st[0].copy_(torch.from_numpy(np.ascontiguousarray(ell_fp32, dtype=np.float32).reshape(B, L, N)))
+    return cases.gpu_solver(inst, init="state", state=st, **kw)
+
+
+def instance(L, conn=synth.GRID8, h=9, w=150, potts=False, batch=2, seed=None):
+    seed = 600 + L if seed is None else seed
+    if potts:
+        return synth.grid_potts_normal(seed, h, L, conn, w=0.6, width=w, batch=batch)
+    return synth.grid_theta_random(seed, h, w, L, conn, batch=batch)
+
+
+def start_states(inst, t=3):
+    """FP32 log q after t oracle steps from q^0, per batch item."""
+    out = []
+    for b in range(inst.batch):
+        model = cases.oracle_model(inst, b)
+        out.append(O.solve(model, inst.alpha, t)[-1].astype(np.float32))
+    return np.stack(out)
+
+
+CASES = [(48, synth.GRID8, False), (64, synth.GRID8, False), (100, synth.GRID4, False),
+         (128, synth.GRID8, False), (48, synth.GRID4, True), (128, synth.GRID8, True)]
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("L,conn,potts", CASES)
+def test_one_step_from_identical_state(L, conn, potts, precision):
+    inst = instance(L, conn, potts=potts)
+    start = start_states(inst)
+    s = solver_from_state(inst, start, precision=precision)
+    assert s.steps_per_launch == 1
+    s.step(1)
+    got = gpu_state(s)
+    worst = 0.0
+    for b in range(inst.batch):
+        ref = O.prox_step(start[b].astype(np.float64), cases.oracle_model(inst, b), inst.alpha)
+        worst = max(worst, cases.max_dq(got[b], ref))
+    print(f"L={L} conn={4 if conn == synth.GRID4 else 8} potts={potts} {precision}: one step max|dq| {worst:.3e}")
+    assert worst <= ONE_STEP[precision], worst
+
+
+@pytest.mark.parametrize("L", [64, 128])
+def test_ten_steps_end_to_end_f32(L):
+    inst = instance(L, h=12, w=70, batch=1)
+    model = cases.oracle_model(inst)
+    ref = O.solve(model, inst.alpha, 10)
+    s = cases.gpu_solver(inst)
+    q = torch.empty_like(s.unary)
+    s.solve(10, q)
+    torch.cuda.synchronize()
+    err = float(np.abs(q.cpu().numpy()[0].astype(np.float64) - np.exp(ref[-1])).max())
+    print(f"L={L}: 10 steps FP32 max|dq| {err:.3e}")
+    assert err <= 1e-5
+    assert s.iteration == 10
+    assert np.abs(q.cpu().numpy().sum(1) - 1.0).max() <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
+def test_ten_steps_end_to_end_message_modes(precision):
+    inst = instance(128, h=12, w=70, batch=1)
+    model = cases.oracle_model(inst)
+    rnd = O.round_to_bf16 if precision == "bf16" else O.round_to_f16
+    exact = O.solve(model, inst.alpha, 10)[-1]
+    rounded = O.solve(model, inst.alpha, 10, operand=rnd)[-1]
+    s = cases.gpu_solver(inst, precision=precision)
+    s.step(10)
+    got = gpu_state(s)[0]
+    e_exact = cases.max_dq(got, exact)
+    e_round = cases.max_dq(got, rounded)
+    effect = cases.max_dq(rounded, exact)
+    print(f"L=128 {precision}: 10 steps max|dq| {e_exact:.3e} to the exact iteration, {e_round:.3e} to the "
+          f"oracle with q rounded alike (the rounding alone moves it {effect:.3e})")
+    assert e_round <= ONE_STEP[precision]
+    assert e_exact <= 1.25 * effect + ONE_STEP[precision] / 4
+
+
+@pytest.mark.parametrize("L", [48, 128])
+def test_init_and_free_energy(L):
+    inst = instance(L, h=10, w=67, batch=2)
+    s = cases.gpu_solver(inst)
+    got = gpu_state(s)
+    for b in range(inst.batch):
+        model = cases.oracle_model(inst, b)
+        assert cases.max_dq(got[b], O.init_state(model.unary)) <= 1e-6
+    s.step(4)
+    F = s.free_energy()
+    ell = gpu_state(s)
+    for b in range(inst.batch):
+        Fr = O.free_energy(ell[b], cases.oracle_model(inst, b))
+        assert abs(F[b] - Fr) <= 1e-10 * max(1.0, abs(Fr)), (b, F[b], Fr)
+    pinst = instance(L, synth.GRID4, h=10, w=67, potts=True, batch=1)
+    p = cases.gpu_solver(pinst)
+    p.step(3)
+    Fp = p.free_energy()[0]
+    Fr = O.free_energy(gpu_state(p)[0], cases.oracle_model(pinst))
+    assert abs(Fp - Fr) <= 1e-10 * max(1.0, abs(Fr))
+
+
+def test_benchmark_shape_one_step_sampled_rows():
+    """512 x 512, L = 128 (the benchmark shape, streamed past the cache): one
+    step against the oracle on row bands at the top, the middle and the
+    bottom, with the full width (eight tiles per row)."""
+    inst = synth.workload_large_labels()
+    s = cases.gpu_solver(inst, steps_per_launch=1)
+    s.step(1)
+    g = gpu_state(s)[0].reshape(128, 512, 512)
+    u = inst.unary[0].astype(np.float64).reshape(128, 512, 512)
+    ell0 = O.init_state(inst.unary[0].astype(np.float64)).reshape(128, 512, 512)
+    th = inst.theta.astype(np.float64)
+    for y0 in (0, 255, 508):
+        lo, hi = max(0, y0 - 1), min(512, y0 + 5)
+        h = hi - lo
+        sub = O.grid_model(u[:, lo:hi, :].reshape(128, -1), h, 512, 8, theta=th)
+        ref = O.prox_step(ell0[:, lo:hi, :].reshape(128, -1), sub, inst.alpha).reshape(128, h, 512)
+        a = 1 if lo > 0 else 0
+        b = h - 1 if hi < 512 else h
+        err = cases.max_dq(g[:, lo:hi, :][:, a:b, :].reshape(128, -1), ref[:, a:b, :].reshape(128, -1))
+        assert err <= 1e-6, (y0, err)
+
+
+def test_step_many_mixes_many_label_handles():
+    from paper_1511_06103_amd import mf
+    insts = [instance(96, h=20, w=90, batch=1), synth.grid_theta_random(3, 40, 33, 21, synth.GRID8),
+             instance(64, synth.GRID4, h=7, w=65, batch=1)]
+    counts = [3, 4, 2]
+    alone = []
+    for inst, k in zip(insts, counts):
+        a = cases.gpu_solver(inst, steps_per_launch=1)
+        a.step(k)
+        alone.append(gpu_state(a))
+    solvers = [cases.gpu_solver(inst) for inst in insts]
+    mf.step_many(solvers, counts)
+    for s, a, k in zip(solvers, alone, counts):
+        assert s.iteration == k
+        np.testing.assert_array_equal(gpu_state(s), a)
+
+
+def test_many_labels_rejected_where_not_implemented():
+    from paper_1511_06103_amd import mf
+    inst = instance(64, batch=1)
+    with pytest.raises(mf.MFError) as e:
+        cases.gpu_solver(inst, rule="adhoc")
+    assert e.value.status == mf.MF_EUNSUPPORTED
+    s = cases.gpu_solver(inst)
+    v = torch.zeros((64, inst.n_nodes), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(mf.MFError) as e:
+        s.lipschitz(v, v, 10)
+    assert e.value.status == mf.MF_EUNSUPPORTED
