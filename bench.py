@@ -13,8 +13,18 @@ Theta, alpha = 0.5 and T = 100 iterations (FP32).
 Prints one JSON line: node-label updates/s = B * N * L * T * K / time, with
 p50/p99 solve latency, the roofline of the dominant kernel (the step kernel
 as the solve launches it, K fused steps per launch, timed over back-to-back
-launches between HIP events on the stream it runs on) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+launches between HIP events on the stream it runs on), the FP64 CPU oracle
+timed on a bounded sample of the same workload, the agreement of the timed
+solve's marginals with the oracle's (``parity``) and, for the default
+workload, the step kernel on the 2048 x 2048 grid whose state does not fit
+the last-level cache (``beyond_cache``).
+
+The roofline's ``bound`` names the limiter from counter readings taken with
+rocprofv3 (profiles/step_kernel_traffic.json, valid while the kernel's
+sources are unchanged): HBM when the bytes the kernel moves below L2 are
+close to its algorithmic bytes; VALU issue when they are far below (the
+state stays in the last-level cache) and the VALU instruction count is
+known; the matrix cores when their issued rate is the larger fraction.
 
 Profiling helpers (single GPU):
     --mode kernel   only the dominant kernel, --launches times (for counters)
@@ -38,12 +48,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
+MFMA_F32_PEAK_TFLOPS = 157.3    # MI355X dense FP32 matrix peak, published
+# wave64 VALU instructions the chip can issue per second: 256 compute units x
+# 4 SIMDs, each a 16-lane SIMD taking 4 cycles per wave64 instruction, 2.4 GHz
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4
 BYTES_PER_UPDATE = 12          # read log q (4) + read u (4) + write log q' (4)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 # sources of each workload's dominant kernel: a traffic measurement holds
 # only while they are unchanged
 KERNEL_SOURCES = {
     "grid": ("grid_temporal.h", "grid_lanes.h", "msg_codec.h"),
+    "large": ("grid_large.hip", "grid_temporal.h", "grid_lanes.h", "msg_codec.h"),
     "csr": ("csr_kernels.hip", "msg_codec.h"),
     "dense": ("dense_kernels.hip",),
 }
@@ -51,6 +66,7 @@ KERNEL_SOURCES = {
 WORKLOADS = {
     "grid256_L21_theta": lambda s: s.workload_c2(),
     "grid2048_L21_theta": lambda s: s.workload_big(),
+    "grid512_L128_theta": lambda s: s.workload_large_labels(),
     "grid32_L2_potts": lambda s: s.workload_c1(),
     "batch16_grid128_L21": lambda s: s.workload_c5(),
     # one step = the forward solve with checkpoints and the adjoint back to u and Theta
@@ -75,6 +91,8 @@ def source_hash(kind="grid"):
 
 
 def source_kind(inst):
+    if inst.graph in (0, 1) and inst.n_labels > 32:
+        return "large"
     return {2: "csr", 3: "dense"}.get(inst.graph, "grid")
 
 
@@ -109,7 +127,7 @@ def algorithmic_bytes(inst, k, precision="f32"):
     return BYTES_PER_UPDATE * B * N * L * k
 
 
-def time_step_launches(solver, torch, launches):
+def time_step_launches(solver, torch, launches, warm=1):
     """Average duration of one launch of the step kernel as the solve runs it:
     each mf_step(K) with K = steps fused per launch is exactly one launch.
     The launches run back to back on the solver's stream between one pair of
@@ -118,7 +136,7 @@ def time_step_launches(solver, torch, launches):
     stream = solver.stream
     k = solver.steps_per_launch
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    solver.step(k)
+    solver.step(k * warm)      # untimed: the first launches touch freshly allocated pages
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         a.record(stream)
@@ -139,6 +157,8 @@ def step_kernel_name(inst, k):
         return "mf::dense_step_kernel + mf::dense_epilogue_kernel"
     if inst.graph == 2:
         return "mf::csr_step_kernel"
+    if L > 32:
+        return "mf::large::large_step_kernel"
     if L <= 8 and N <= 1024 and k > 4:   # the fused kernels take at most 4 steps
         return "mf::whole_grid_kernel"
     if k == 1:
@@ -271,10 +291,10 @@ def cpu_baseline(inst, budget_s=8.0):
             "host": {"cpu_count": os.cpu_count(), "cpu_model": cpu_model()}}
 
 
-def load_traffic(workload, k, kind, precision="f32"):
-    """HBM bytes per launch of the dominant kernel measured with rocprofv3
-    counters (profiles/), or None when none was taken for this workload,
-    launch depth and message precision or the kernel sources changed since."""
+def load_counters(workload, k, kind, precision="f32"):
+    """The rocprofv3 readings of the dominant kernel for this workload, launch
+    depth and message precision (profiles/step_kernel_traffic.json), or None
+    when none were taken or the kernel's sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -284,8 +304,149 @@ def load_traffic(workload, k, kind, precision="f32"):
         if (e.get("workload") == workload and e.get("steps_per_launch") == k
                 and e.get("precision", "f32") == precision
                 and e.get("kernel_source_sha256_16") == source_hash(kind)):
-            return e.get("hbm_bytes_per_launch")
+            return e
     return None
+
+
+def load_traffic(workload, k, kind, precision="f32"):
+    """HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE,
+    scaled by a plain copy's readings), or None (see load_counters)."""
+    e = load_counters(workload, k, kind, precision)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def mfma_flops_per_launch(inst, k, precision):
+    """Flops the matrix cores issue per launch of the step kernel, and the
+    algorithmic flops of the contraction they serve, or None when the kernel
+    has no matrix-core product.  Dense: K Q with N rounded up to 64, 32 label
+    slots, one product per BF16 plane of q.  Many labels: Theta S over the
+    label count rounded up to 64 or 128, once in FP32 or three times (the
+    hi / lo parts) in BF16."""
+    B, L, N = inst.unary.shape
+    if inst.graph == 3:
+        Np = -(-N // 64) * 64
+        planes = {"f32": 3, "f16": 2, "bf16": 1}[precision]
+        return {"issued": 2.0 * B * Np * Np * 32 * planes, "algorithmic": 2.0 * B * N * N * L,
+                "peak": MFMA_BF16_PEAK_TFLOPS, "type": "bf16"}
+    if inst.graph in (0, 1) and L > 32:
+        LP = 64 if L <= 64 else 128
+        W, H = inst.width, inst.height
+        nodes = B * H * (-(-W // 64) * 64)
+        per = 2.0 * LP * LP * nodes * k
+        f32 = precision == "f32"
+        return {"issued": per * (1 if f32 else 3), "algorithmic": 2.0 * B * N * L * L * k,
+                "peak": MFMA_F32_PEAK_TFLOPS if f32 else MFMA_BF16_PEAK_TFLOPS, "type": "f32" if f32 else "bf16"}
+    return None
+
+
+def roofline_object(inst, k, precision, mean_d, launches, kname, counters):
+    """The dominant kernel against the chip's peaks: its algorithmic HBM bytes,
+    its matrix-core flops and, from counters, its VALU issue, each over the
+    launch time measured here; ``bound`` is the resource that limits it."""
+    algo = algorithmic_bytes(inst, k, precision)
+    hbm = algo / mean_d / 1e9
+    traffic = None if counters is None else counters.get("hbm_bytes_per_launch")
+    out = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname, "steps_per_launch": k,
+           "timing": f"mean of {launches} back-to-back launches between two HIP events on the solver's stream",
+           "launch_us_mean": round(mean_d * 1e6, 3), "algorithmic_bytes_per_launch": algo,
+           "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(hbm / HBM_PEAK_GBS, 4),
+                   "traffic_over_algorithmic": None if traffic is None else round(traffic / algo, 3)}}
+    fl = mfma_flops_per_launch(inst, k, precision)
+    if fl is not None:
+        issued = fl["issued"] / mean_d / 1e12
+        out["mfma"] = {"unit": "TFLOP/s", "type": fl["type"], "peak": fl["peak"], "issued": round(issued, 1),
+                       "issued_frac": round(issued / fl["peak"], 4),
+                       "algorithmic": round(fl["algorithmic"] / mean_d / 1e12, 1),
+                       "algorithmic_frac": round(fl["algorithmic"] / mean_d / 1e12 / fl["peak"], 4)}
+    valu = None if counters is None else counters.get("sq_insts_valu_per_launch")
+    if valu is not None:
+        rate = valu / mean_d / 1e9
+        out["valu"] = {"unit": "G wave64 instr/s", "peak": round(VALU_ISSUE_PEAK_G, 1), "achieved": round(rate, 1),
+                       "frac": round(rate / VALU_ISSUE_PEAK_G, 4), "insts_per_launch": valu}
+    if counters is not None and counters.get("rocprof_avg_us"):
+        ra = counters["rocprof_avg_us"] * 1e-6
+        out["rocprof"] = {"avg_us": counters["rocprof_avg_us"], "hbm_frac": round(algo / ra / 1e9 / HBM_PEAK_GBS, 4),
+                          "summary": counters.get("rocprof_summary")}
+        if valu is not None:
+            out["rocprof"]["valu_frac"] = round(valu / ra / 1e9 / VALU_ISSUE_PEAK_G, 4)
+    # the limiter: HBM unless the counters show the state staying in the
+    # cache (then VALU issue, when counted), or the matrix cores run at a
+    # larger fraction of their peak
+    cache_resident = traffic is not None and traffic < 0.5 * algo
+    if cache_resident and "valu" in out:
+        v = out["valu"]
+        out.update(bound="valu_issue", achieved=v["achieved"], peak=v["peak"], unit=v["unit"], frac=v["frac"])
+        if "rocprof" in out:
+            out["rocprof"]["frac"] = out["rocprof"]["valu_frac"]
+    elif "mfma" in out and out["mfma"]["issued_frac"] > out["hbm"]["frac"] and inst.graph != 3:
+        m = out["mfma"]
+        out.update(bound="mfma", achieved=m["issued"], peak=m["peak"], unit="TFLOP/s", frac=m["issued_frac"])
+    elif "rocprof" in out:
+        out["rocprof"]["frac"] = out["rocprof"]["hbm_frac"]
+    if cache_resident and out["bound"] == "hbm":
+        out["note"] = "the state stays in the last-level cache: HBM is not the limiter, VALU counters not taken"
+    return out
+
+
+def beyond_cache(torch, mf, synth, launches):
+    """The single-step kernel on the 2048 x 2048, L = 21 grid (same recipe as
+    the default workload, seed 20): its three arrays of a step (1.06 GB)
+    exceed the 256 MB last-level cache, so the step is a stream through HBM.
+    Timed like the dominant kernel: back-to-back launches between two HIP
+    events on the solver's stream."""
+    inst = synth.workload_big()
+    solver = make_solver(inst, torch, mf)
+    solver.solve(0)
+    mean_d, k = time_step_launches(solver, torch, launches, warm=10)
+    kname = step_kernel_name(inst, k)
+    counters = load_counters(inst.name, k, source_kind(inst))
+    r = roofline_object(inst, k, "f32", mean_d, launches, kname, counters)
+    log(f"beyond the cache: {kname} on 2048 x 2048: {mean_d * 1e6:.2f} us per step, "
+        f"{r['hbm']['achieved']:.0f} GB/s, {r['frac']:.3f} of peak")
+    solver.close()
+    return {"workload": inst.name, "height": inst.height, "width": inst.width, "labels": inst.n_labels, **r}
+
+
+def parity_check(inst, q_gpu, precision):
+    """The timed solve's marginals (problem 0 of the batch) against the FP64
+    oracle run for the same T from the same q^0, with the oracle's own
+    arithmetic run in FP32 as the rounding floor of an FP32 iteration.
+    Returns max |dq|, the floor, the bound (1e-5 or twice the floor,
+    whichever is larger) and the fraction of nodes whose most likely label
+    agrees.  BF16 / FP16 messages at alpha = 0.5 over 100 steps are not
+    comparable element by element (rounding can switch basins), so there
+    only the figures are reported."""
+    import oracle as O
+    t0 = time.perf_counter()
+    if inst.graph in (0, 1):
+        th = None if inst.theta is None else inst.theta.astype(np.float64)
+        model = O.grid_model(inst.unary[0].astype(np.float64), inst.height, inst.width,
+                             4 if inst.graph == 0 else 8, theta=th, potts_w=None if th is not None else inst.potts_w)
+    elif inst.graph == 2:
+        model = O.csr_model(inst.unary[0].astype(np.float64), inst.row_ptr, inst.col, inst.csr_w,
+                            theta=inst.theta.astype(np.float64))
+    else:
+        K = O.round_to_bf16(O.gaussian_kernel(inst.features))
+        cooc = None if inst.cooc is None else inst.cooc.astype(np.float64)
+        model = O.dense_model(inst.unary[0].astype(np.float64), K, potts_w=inst.potts_w, cooc=cooc)
+    ref = O.solve(model, inst.alpha, inst.iters)[-1]
+    floor_run = O.solve(model.astype(np.float32), np.float32(inst.alpha), inst.iters)[-1]
+    q = np.asarray(q_gpu[0], dtype=np.float64)
+    qr = np.exp(ref)
+    err = float(np.abs(q - qr).max())
+    floor = float(np.abs(np.exp(floor_run.astype(np.float64)) - qr).max())
+    agree = float((q.argmax(0) == qr.argmax(0)).mean())
+    out = {"oracle": f"FP64, the same instance and q^0, {inst.iters} steps ({time.perf_counter() - t0:.1f} s)",
+           "max_abs_dq": err, "fp32_floor_max_abs_dq": floor, "argmax_agreement": agree,
+           "messages": precision}
+    if precision == "f32":
+        bound = max(1e-5, 2.0 * floor)
+        out.update(bound=bound, passed=bool(err <= bound and agree >= 0.999))
+    else:
+        out.update(bound=None, passed=None)
+    return out
 
 
 def main():
@@ -297,7 +458,10 @@ def main():
     ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "copy"])
     ap.add_argument("--launches", type=int, default=200)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's timing and the parity check")
+    ap.add_argument("--no-beyond-cache", action="store_true", help="skip the 2048 x 2048 step measurement")
+    ap.add_argument("--launches-big", type=int, default=40,
+                    help="back-to-back launches timed on the 2048 x 2048 grid")
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16", "f16"],
                     help="neighbour-message precision (the state and the step stay FP32)")
     args = ap.parse_args()
@@ -366,33 +530,27 @@ def main():
 
     # dominant kernel: one step-kernel launch = K steps over all B * N * L node-labels
     mean_d, k = time_step_launches(solver, torch, args.launches)
-    algo = algorithmic_bytes(inst, k, args.precision)
-    achieved = algo / mean_d / 1e9
-    traffic = load_traffic(inst.name, k, source_kind(inst), args.precision)
     kname = step_kernel_name(inst, k)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kname, "steps_per_launch": k, "launch_us_mean": round(mean_d * 1e6, 3),
-                "algorithmic_bytes_per_launch": algo}
+    counters = load_counters(inst.name, k, source_kind(inst), args.precision)
+    roofline = roofline_object(inst, k, args.precision, mean_d, args.launches, kname, counters)
     log(f"{kname} (K={k}): {mean_d * 1e6:.2f} us mean per launch over {args.launches} back-to-back "
-        f"launches -> {achieved:.0f} GB/s")
-    if inst.graph == 3:
-        # the K Q product on the BF16 matrix cores: what they issue (N rounded
-        # up to 64, 32 label slots, one product per BF16 plane of q) and the
-        # algorithmic 2 N^2 L, both per launch over the same launch time
-        Np = -(-N // 64) * 64
-        planes = {"f32": 3, "f16": 2, "bf16": 1}[args.precision]
-        issued = 2.0 * B * Np * Np * 32 * planes / mean_d / 1e12
-        algo_fl = 2.0 * B * N * N * L / mean_d / 1e12
-        roofline["mfma"] = {"unit": "TFLOP/s", "peak": MFMA_BF16_PEAK_TFLOPS, "issued": round(issued, 1),
-                            "issued_frac": round(issued / MFMA_BF16_PEAK_TFLOPS, 4),
-                            "algorithmic": round(algo_fl, 1),
-                            "algorithmic_frac": round(algo_fl / MFMA_BF16_PEAK_TFLOPS, 4)}
+        f"launches -> {roofline['hbm']['achieved']:.0f} GB/s algorithmic; bound {roofline['bound']} "
+        f"at {roofline['frac']:.3f} of peak")
+    q_host = q.cpu().numpy()
+
+    beyond = None
+    if args.workload == "grid256_L21_theta" and not args.no_beyond_cache:
+        del solver
+        torch.cuda.empty_cache()
+        beyond = beyond_cache(torch, mf, synth, args.launches_big)
 
     cpu = None
+    parity = None
     if not args.no_cpu:
         cpu = cpu_baseline(inst)
         log(f"cpu oracle: {cpu['value']:.3e} updates/s ({cpu['sample']})")
+        parity = parity_check(inst, q_host, args.precision)
+        log(f"parity against the FP64 oracle: {parity}")
 
     out = {
         "metric": METRIC,
@@ -412,6 +570,8 @@ def main():
         "config": dict(workload_config(inst, "init + iters proximal steps + write q"), messages=args.precision),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "parity": parity,
+        "beyond_cache": beyond,
     }
     print(json.dumps(out), flush=True)
 

@@ -10,18 +10,22 @@
 // against 12 bytes of state and unaries, a real dense contraction
 // [L x L] x [L x nodes]: it runs on MFMA, the rest of the step on the VALU.
 //
-// A workgroup (four wavefronts) owns a tile of 64 consecutive nodes of one
-// grid row.  The labels are taken in chunks of 32: for each chunk the
-// workgroup stages q = exp(log q) of the tile's three rows (the row and
-// its neighbours above and below, 66 nodes each, off-grid q = 0) in LDS,
-// forms the chunk of S for its 64 nodes in LDS, and every wavefront
-// multiplies that S chunk by the matching columns of Theta into its
-// accumulators.  Wavefront w owns the output label blocks w, w + 4 (16
-// labels each) for all 64 nodes; its rows of Theta stay in registers for
-// the whole launch.  The per-node log-sum-exp runs over the accumulators
-// of the four wavefronts: a max and a sum inside each (lanes x, x ^ 16,
-// x ^ 32, x ^ 48 with the gfx950 row-swap permutes), combined across
-// wavefronts through LDS.
+// A tile is 64 consecutive nodes of one grid row.  A workgroup has one
+// wavefront per block of 16 output labels (L rounded up to 64 or 128: four
+// or eight wavefronts) and works through tiles one after another, two
+// workgroups per compute unit for the whole launch; wavefront w keeps its
+// rows 16 w .. 16 w + 15 of Theta in registers throughout.  The labels of a
+// tile are taken in chunks of 32: for each chunk the workgroup stages
+// q = exp(log q) of the tile's three rows (the row and its neighbours above
+// and below, 66 nodes each, off-grid q = 0) in LDS, forms the chunk of S for
+// its 64 nodes in LDS, and every wavefront multiplies that S chunk by the
+// matching columns of its Theta rows into its accumulators.  The loads of
+// the next chunk (or, in the last chunk, the unaries and the first chunk of
+// the next tile) are in flight while a chunk is summed and multiplied.  The
+// tile's own log q, staged with the middle row, stays in LDS for the step.
+// The per-node log-sum-exp runs over the accumulators of all wavefronts: a
+// max and a sum inside each (lanes x, x ^ 16, x ^ 32, x ^ 48 with the gfx950
+// row-swap permutes), combined across wavefronts through LDS.
 //
 // Products.  FP32 messages: v_mfma_f32_16x16x4f32 on FP32 Theta and S, so
 // the step keeps FP32 accuracy.  BF16 / FP16 messages: q is rounded to the
@@ -43,12 +47,33 @@ namespace mf {
 namespace large {
 
 constexpr int kTN = 64;             // nodes per tile (one row segment)
-constexpr int kNT = 256;            // threads per workgroup
 constexpr int kKC = 32;             // labels per chunk
 constexpr int kRW = kTN + 2;        // region row: the tile and one node either side
 constexpr int kRP = 3 * kRW;        // region nodes per label plane (three rows)
 constexpr int kRegion = kKC * kRP;  // staged q values per chunk
-constexpr int kLoads = (kRegion + kNT - 1) / kNT;
+
+constexpr int kSegs = kKC * 3;     // (label, row) segments of a chunk's region
+
+// Wavefronts: one per block of 16 output labels and half tile (32 nodes),
+// 2 LP / 16 in all; LP = 128 runs one workgroup per compute unit, LP = 64
+// two, so that a SIMD holds four wavefronts either way.
+template <int LP>
+struct Geo {
+  static constexpr int NOB = LP / 16;        // output label blocks
+  static constexpr int NW = 2 * NOB;         // wavefronts per workgroup
+  static constexpr int NT = 64 * NW;
+  static constexpr int SEGS = kSegs / NW;    // region segments staged per wavefront
+  static constexpr int WG_PER_CU = LP == 128 ? 1 : 2;
+  static constexpr int WAVES_PER_SIMD = NW * WG_PER_CU / 4;
+};
+
+// One chunk's region in registers: the 64 tile columns of SEGS segments
+// (lane = column) and one of the 2 x 96 edge columns (threads < 192).
+template <int LP>
+struct Region {
+  float v[Geo<LP>::SEGS];
+  float edge;
+};
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -78,218 +103,310 @@ __device__ inline void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
   lo = __builtin_bit_cast(bf16x8, l);
 }
 
+// Four wavefronts per SIMD, which bounds the registers of a wavefront.
 template <int LP, int CONN, int PREC, bool STREAM>
-__global__ __launch_bounds__(kNT) void large_step_kernel(StepArgs a, float one_minus_alpha, int potts) {
+__global__ __launch_bounds__(Geo<LP>::NT)
+__attribute__((amdgpu_waves_per_eu(Geo<LP>::WAVES_PER_SIMD, Geo<LP>::WAVES_PER_SIMD)))
+void large_step_kernel(StepArgs a, float one_minus_alpha, int potts) {
   using M = MsgT<PREC>;
   using T = typename M::T;
   constexpr bool F32 = PREC == P_F32;
-  constexpr int NOB = LP / 64;       // output blocks of 16 labels per wavefront
+  constexpr int NOB = Geo<LP>::NOB, NW = Geo<LP>::NW, SEGS = Geo<LP>::SEGS;
   constexpr int NC = LP / kKC;       // label chunks
-  constexpr int NNB = kTN / 16;      // node blocks of 16 per tile
+  constexpr int NNB = 2;             // node blocks of 16 per wavefront (half a tile)
   constexpr int SST = s_stride<PREC>();
+  constexpr int LS = kTN + 4;        // row stride of the own-row log q: rows 4 g + i on disjoint banks
   __shared__ T qs[kRegion];
+  __shared__ float ls[LP * LS];
   __shared__ float ss[kKC * SST];
-  __shared__ float red_m[4][kTN], red_s[4][kTN];
+  __shared__ float red_m[NOB][kTN], red_s[NOB][kTN];
 
   const int L = a.L;
   const unsigned N = (unsigned)a.N;
   const int H = a.H, W = a.W;
   const int tiles_x = (W + kTN - 1) / kTN;
-  const int tile = lanes::xcd_tile(blockIdx.x, tiles_x * H * a.B);
-  const int b = tile / (tiles_x * H);
-  const int tr = tile - b * (tiles_x * H);
-  const int y = tr / tiles_x;
-  const int x0 = (tr - y * tiles_x) * kTN;
-  const size_t base = (size_t)b * L * N;
-  const float* __restrict__ lin = a.state_in + base;
-  const float* __restrict__ ug = a.unary + base;
+  const int total = tiles_x * H * a.B;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ob = wave % NOB;         // output labels 16 ob .. 16 ob + 15
+  const int half = wave / NOB;       // tile nodes 32 half .. 32 half + 31
   const int c = lane & 15, g = lane >> 4;
 
-  // Theta rows of this wavefront's output blocks (label 16 (wave + 4 ob) + c),
-  // zero outside L x L; Potts builds w (1 1^T - I).
-  auto theta_at = [&](int row, int col) -> float {
-    if (row >= L || col >= L) return 0.f;
-    if (potts) return row == col ? 0.f : a.potts_w;
-    return a.theta[row * L + col];
+  // Theta rows of this wavefront's output block (label 16 ob + c), held for
+  // every tile of the launch; zero outside L x L; Potts builds w (1 1^T - I).
+  const int trow = 16 * ob + c;
+  // every lane loads (no divergent branch around the loads); with Potts
+  // (theta may be NULL) the load reads the unaries' first element instead
+  const float* thp = potts ? a.unary : a.theta;
+  auto theta_at = [&](int col) -> float {
+    const bool ok = trow < L && col < L;
+    const float t = thp[(ok && !potts) ? trow * L + col : 0];
+    return !ok ? 0.f : potts ? (trow == col ? 0.f : a.potts_w) : t;
   };
-  float tha[F32 ? NOB : 1][F32 ? LP / 4 : 1];
-  bf16x8 thh[F32 ? 1 : NOB][F32 ? 1 : NC], thl[F32 ? 1 : NOB][F32 ? 1 : NC];
+  float tha[F32 ? LP / 4 : 1];
+  bf16x8 thh[F32 ? 1 : NC], thl[F32 ? 1 : NC];
+  if constexpr (F32) {
+    // A of k-step kb: Theta[row][4 kb + g]
 #pragma unroll
-  for (int ob = 0; ob < NOB; ++ob) {
-    const int row = 16 * (wave + 4 * ob) + c;
-    if constexpr (F32) {
-      // A of k-step kb: Theta[row][4 kb + g]
+    for (int kb = 0; kb < LP / 4; ++kb) tha[kb] = theta_at(4 * kb + g);
+  } else {
+    // A of chunk kc: Theta[row][32 kc + 8 g + e], e < 8
 #pragma unroll
-      for (int kb = 0; kb < LP / 4; ++kb) tha[ob][kb] = theta_at(row, 4 * kb + g);
-    } else {
-      // A of chunk kc: Theta[row][32 kc + 8 g + e], e < 8
+    for (int kc = 0; kc < NC; ++kc) {
+      float t[8];
 #pragma unroll
-      for (int kc = 0; kc < NC; ++kc) {
-        float t[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) t[e] = theta_at(row, kKC * kc + 8 * g + e);
-        split8(t, thh[ob][kc], thl[ob][kc]);
-      }
+      for (int e = 0; e < 8; ++e) t[e] = theta_at(kKC * kc + 8 * g + e);
+      split8(t, thh[kc], thl[kc]);
     }
   }
 
-  f32x4 acc[NOB][NNB];
+  // Tile i of this workgroup: tiles are dealt XCD by XCD (lanes::xcd_tile);
+  // the grid is a multiple of 8 workgroups, so a workgroup stays on the
+  // XCD range it starts in.
+  struct Tile {
+    int y, x0;
+    const float* lin;
+    const float* ug;
+    float* out;
+    unsigned row_n;
+  };
+  auto tile_of = [&](int i) {
+    Tile t;
+    const int tile = lanes::xcd_tile(i, total);
+    const int b = tile / (tiles_x * H);
+    const int tr = tile - b * (tiles_x * H);
+    t.y = tr / tiles_x;
+    t.x0 = (tr - t.y * tiles_x) * kTN;
+    const size_t base = (size_t)b * L * N;
+    t.lin = a.state_in + base;
+    t.ug = a.unary + base;
+    t.out = a.state_out + base;
+    t.row_n = (unsigned)(t.y * W);
+    return t;
+  };
+
+  // log q of chunk kc's 32 labels on the three rows y - 1, y, y + 1, nodes
+  // x0 - 1 .. x0 + 64; off-grid nodes and labels >= L read as -inf (q = 0).
+  // Segment s = (label kk = s / 3, row = s % 3) of the chunk goes to
+  // wavefront s % NW: its (label, row) is uniform, its lanes are the 64
+  // tile columns; the two edge columns of every segment go to threads
+  // 0 .. 191.  Loads at 32-bit byte offsets from the tile's uniform base.
+  auto load_region = [&](const Tile& t, int kc, Region<LP>& rg) {
+    const int gx = t.x0 + lane;
+    const bool col_ok = gx < W;
 #pragma unroll
-  for (int ob = 0; ob < NOB; ++ob)
+    for (int j = 0; j < SEGS; ++j) {
+      const int seg = wave + NW * j;
+      const int kk = seg / 3, row = seg - 3 * (seg / 3);
+      const int l = kKC * kc + kk, gy = t.y + row - 1;
+      const bool ok = col_ok && l < L && gy >= 0 && gy < H;
+      const unsigned off = ok ? ((unsigned)l * N + (unsigned)(gy * W + gx)) * 4u : 0u;
+      const float x = temporal::load_at(t.lin, off);
+      rg.v[j] = ok ? x : -INFINITY;
+    }
+    const int e = (int)temporal::opaque((unsigned)tid);
+    const int seg = e >> 1;
+    const int kk = seg / 3, row = seg - 3 * (seg / 3);
+    const int l = kKC * kc + kk, gy = t.y + row - 1, ex = (e & 1) ? t.x0 + kTN : t.x0 - 1;
+    const bool ok = e < 2 * kSegs && l < L && gy >= 0 && gy < H && ex >= 0 && ex < W;
+    const unsigned off = ok ? ((unsigned)l * N + (unsigned)(gy * W + ex)) * 4u : 0u;
+    const float x = temporal::load_at(t.lin, off);
+    rg.edge = ok ? x : -INFINITY;
+  };
+  // q to the staging buffer, and the tile's own log q (the middle row) kept
+  // for the epilogue
+  auto store_region = [&](int kc, const Region<LP>& rg) {
 #pragma unroll
-    for (int nb = 0; nb < NNB; ++nb) acc[ob][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < SEGS; ++j) {
+      const int seg = wave + NW * j;
+      const int kk = seg / 3, row = seg - 3 * (seg / 3);
+      qs[kk * kRP + row * kRW + 1 + lane] = M::enc(__expf(rg.v[j]));   // exp(-inf) = 0
+      if (row == 1) ls[(kKC * kc + kk) * LS + lane] = rg.v[j];
+    }
+    const int e = tid;
+    if (e < 2 * kSegs) {
+      const int seg = e >> 1;
+      const int kk = seg / 3, row = seg - 3 * (seg / 3);
+      qs[kk * kRP + row * kRW + ((e & 1) ? kRW - 1 : 0)] = M::enc(__expf(rg.edge));
+    }
+  };
+  // accumulator i of node block nb is label 16 ob + 4 g + i at node
+  // x0 + 16 (2 half + nb) + c (clamped into the grid; masked at the store)
+  auto unary_at = [&](const Tile& t, int nb, int i) -> const float* {
+    const int x = t.x0 + 16 * (2 * half + nb) + c;
+    const int l = 16 * ob + 4 * g + i;
+    const unsigned off = ((unsigned)(l < L ? l : L - 1) * N + t.row_n + (unsigned)(x < W ? x : W - 1)) * 4u;
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(t.ug) + off);
+  };
+
+  int i = blockIdx.x;
+  if (i >= total) return;
+  Tile cur = tile_of(i);
+  {
+    Region<LP> rg;
+    load_region(cur, 0, rg);
+    store_region(0, rg);
+  }
+  __syncthreads();   // chunk 0 of the first tile staged
+
+  for (;;) {
+    const int inext = i + (int)gridDim.x;
+    const bool has_next = inext < total;
+    const Tile nxt = tile_of(has_next ? inext : i);
+    f32x4 acc[NNB];
+#pragma unroll
+    for (int nb = 0; nb < NNB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float uu[NNB][4];
+    Region<LP> v;
 
 #pragma unroll
-  for (int kc = 0; kc < NC; ++kc) {
-    // q of the chunk's 32 labels on the three rows y - 1, y, y + 1, nodes
-    // x0 - 1 .. x0 + 64; off-grid nodes and labels >= L hold q = 0
-    float v[kLoads];
+    for (int kc = 0; kc < NC; ++kc) {
+      // in flight during this chunk's S and products: the next chunk's
+      // region, or, in the last chunk, the unaries of the epilogue and the
+      // first chunk of the next tile
+      if (kc + 1 < NC) {
+        load_region(cur, kc + 1, v);
+      } else {
 #pragma unroll
-    for (int r = 0; r < kLoads; ++r) {
-      const int f = tid + r * kNT;
-      const int kk = f / kRP;
-      const int rem = f - kk * kRP;
-      const int row = rem / kRW;
-      const int col = rem - row * kRW;
-      const int l = kKC * kc + kk;
-      const int gy = y + row - 1, gx = x0 + col - 1;
-      const bool ok = f < kRegion && l < L && gy >= 0 && gy < H && gx >= 0 && gx < W;
-      const float x = lin[ok ? (unsigned)l * N + (unsigned)(gy * W + gx) : 0u];
-      v[r] = ok ? x : -INFINITY;
-    }
+        for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
-    for (int r = 0; r < kLoads; ++r) {
-      const int f = tid + r * kNT;
-      if (f < kRegion) qs[f] = M::enc(__expf(v[r]));   // exp(-inf) = 0
-    }
-    __syncthreads();   // q staged; every wavefront is past the previous chunk's products
+          for (int j = 0; j < 4; ++j) {
+            const float* pu = unary_at(cur, nb, j);
+            uu[nb][j] = STREAM ? __builtin_nontemporal_load(pu) : *pu;
+          }
+        if (has_next) load_region(nxt, 0, v);
+      }
 
-    // S chunk: wavefront w forms labels w + 4 j of the chunk, lane = node
+      // S chunk: wavefront w forms labels w + NW j of the chunk, lane = node
 #pragma unroll
-    for (int j = 0; j < kKC / 4; ++j) {
-      const int kk = wave + 4 * j;
-      const T* q = qs + kk * kRP + lane + 1;           // row y - 1 at node lane
-      float s = M::dec(q[0]) + M::dec(q[2 * kRW]) + M::dec(q[kRW - 1]) + M::dec(q[kRW + 1]);
-      if (CONN == 8) s += (M::dec(q[-1]) + M::dec(q[1])) + (M::dec(q[2 * kRW - 1]) + M::dec(q[2 * kRW + 1]));
-      ss[kk * SST + lane] = s;
-    }
-    __syncthreads();   // S chunk complete
+      for (int j = 0; j < kKC / NW; ++j) {
+        const int kk = wave + NW * j;
+        const T* q = qs + kk * kRP + lane + 1;           // row y - 1 at node lane
+        float sv = M::dec(q[0]) + M::dec(q[2 * kRW]) + M::dec(q[kRW - 1]) + M::dec(q[kRW + 1]);
+        if (CONN == 8) sv += (M::dec(q[-1]) + M::dec(q[1])) + (M::dec(q[2 * kRW - 1]) + M::dec(q[2 * kRW + 1]));
+        ss[kk * SST + lane] = sv;
+      }
+      __syncthreads();   // S chunk complete; every wavefront is done reading q
 
-    if constexpr (F32) {
+      if constexpr (F32) {
 #pragma unroll
-      for (int nb = 0; nb < NNB; ++nb) {
+        for (int nb = 0; nb < NNB; ++nb) {
 #pragma unroll
-        for (int kb = 0; kb < kKC / 4; ++kb) {
-          const float bv = ss[(4 * kb + g) * SST + 16 * nb + c];
+          for (int kb = 0; kb < kKC / 4; ++kb) {
+            const float bv = ss[(4 * kb + g) * SST + 16 * (2 * half + nb) + c];
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(tha[(kKC / 4) * kc + kb], bv, acc[nb], 0, 0, 0);
+          }
+        }
+      } else {
 #pragma unroll
-          for (int ob = 0; ob < NOB; ++ob)
-            acc[ob][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(tha[ob][(kKC / 4) * kc + kb], bv, acc[ob][nb], 0, 0, 0);
+        for (int nb = 0; nb < NNB; ++nb) {
+          float sv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) sv[e] = ss[(8 * g + e) * SST + 16 * (2 * half + nb) + c];
+          bf16x8 sh, sl;
+          split8(sv, sh, sl);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(thh[kc], sh, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(thh[kc], sl, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(thl[kc], sh, acc[nb], 0, 0, 0);
         }
       }
-    } else {
-#pragma unroll
-      for (int nb = 0; nb < NNB; ++nb) {
-        float sv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) sv[e] = ss[(8 * g + e) * SST + 16 * nb + c];
-        bf16x8 sh, sl;
-        split8(sv, sh, sl);
-#pragma unroll
-        for (int ob = 0; ob < NOB; ++ob) {
-          acc[ob][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(thh[ob][kc], sh, acc[ob][nb], 0, 0, 0);
-          acc[ob][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(thh[ob][kc], sl, acc[ob][nb], 0, 0, 0);
-          acc[ob][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(thl[ob][kc], sh, acc[ob][nb], 0, 0, 0);
-        }
+      if (kc + 1 < NC) {
+        store_region(kc + 1, v);
+        __syncthreads();   // next chunk staged; every wavefront is done reading this S chunk
       }
     }
-  }
 
-  // Epilogue.  Accumulator i of (ob, nb) is label 16 (wave + 4 ob) + 4 g + i
-  // at node x0 + 16 nb + c.
-  const unsigned row_n = (unsigned)(y * W);
-  float z[NOB][NNB][4];
+    // Epilogue: the damped step and the per-node log-sum-exp over the NOB
+    // output blocks of the node's half.
+    float z[NNB][4];
 #pragma unroll
-  for (int nb = 0; nb < NNB; ++nb) {
-    const int x = x0 + 16 * nb + c;
-    const unsigned n = row_n + (unsigned)(x < W ? x : W - 1);
+    for (int nb = 0; nb < NNB; ++nb) {
 #pragma unroll
-    for (int ob = 0; ob < NOB; ++ob) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int l = 16 * (wave + 4 * ob) + 4 * g + i;
-        const unsigned o = (unsigned)(l < L ? l : L - 1) * N + n;
-        const float e = lin[o];
-        const float u = STREAM ? __builtin_nontemporal_load(&ug[o]) : ug[o];
-        const float zz = one_minus_alpha * e - a.alpha * (u + acc[ob][nb][i]);
-        z[ob][nb][i] = l < L ? zz : -INFINITY;
+      for (int j = 0; j < 4; ++j) {
+        const int l = 16 * ob + 4 * g + j;
+        const float e = ls[(l < LP ? l : LP - 1) * LS + 16 * (2 * half + nb) + c];
+        const float zz = one_minus_alpha * e - a.alpha * (uu[nb][j] + acc[nb][j]);
+        z[nb][j] = l < L ? zz : -INFINITY;
       }
     }
-  }
-  float mx[NNB], se[NNB];
 #pragma unroll
-  for (int nb = 0; nb < NNB; ++nb) {
-    float m = z[0][nb][0];
+    for (int nb = 0; nb < NNB; ++nb) {
+      float m = z[nb][0];
 #pragma unroll
-    for (int ob = 0; ob < NOB; ++ob)
+      for (int j = 1; j < 4; ++j) m = fmaxf(m, z[nb][j]);
+      m = temporal::rows_max(m);
+      // a block whose labels all lie past L (or a node past the grid's edge)
+      // has m = -inf and contributes 0
+      const float mref = m == -INFINITY ? 0.f : m;
+      float sm = 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) m = fmaxf(m, z[ob][nb][i]);
-    m = temporal::rows_max(m);
-    // a wavefront whose labels all lie past L has m = -inf and contributes 0
-    const float mref = m == -INFINITY ? 0.f : m;
-    float s = 0.f;
-#pragma unroll
-    for (int ob = 0; ob < NOB; ++ob)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) s += __expf(z[ob][nb][i] - mref);
-    s = temporal::rows_sum(s);
-    mx[nb] = m;
-    se[nb] = s;
-    if (g == 0) {
-      red_m[wave][16 * nb + c] = m;
-      red_s[wave][16 * nb + c] = s;
+      for (int j = 0; j < 4; ++j) sm += __expf(z[nb][j] - mref);
+      sm = temporal::rows_sum(sm);
+      if (g == 0) {
+        red_m[ob][16 * (2 * half + nb) + c] = m;
+        red_s[ob][16 * (2 * half + nb) + c] = sm;
+      }
     }
-  }
-  __syncthreads();
-  float* __restrict__ out = a.state_out + base;
+    __syncthreads();
 #pragma unroll
-  for (int nb = 0; nb < NNB; ++nb) {
-    const int p = 16 * nb + c;
-    float M = red_m[0][p];
+    for (int nb = 0; nb < NNB; ++nb) {
+      const int p = 16 * (2 * half + nb) + c;
+      float Mx = red_m[0][p];
 #pragma unroll
-    for (int w = 1; w < 4; ++w) M = fmaxf(M, red_m[w][p]);
-    float tot = 0.f;
+      for (int w = 1; w < NOB; ++w) Mx = fmaxf(Mx, red_m[w][p]);
+      float tot = 0.f;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const float mw = red_m[w][p];
-      tot += mw == -INFINITY ? 0.f : red_s[w][p] * __expf(mw - M);
-    }
-    const float lse = M + __logf(tot);
-    const int x = x0 + p;
-    if (x < W) {
-      const unsigned n = row_n + (unsigned)x;
+      for (int w = 0; w < NOB; ++w) {
+        const float mw = red_m[w][p];
+        tot += mw == -INFINITY ? 0.f : red_s[w][p] * __expf(mw - Mx);
+      }
+      const float lse = Mx + __logf(tot);
+      const int x = cur.x0 + p;
+      if (x < W) {
+        const unsigned n = cur.row_n + (unsigned)x;
 #pragma unroll
-      for (int ob = 0; ob < NOB; ++ob) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int l = 16 * (wave + 4 * ob) + 4 * g + i;
+        for (int j = 0; j < 4; ++j) {
+          const int l = 16 * ob + 4 * g + j;
           if (l < L) {
-            if constexpr (STREAM) __builtin_nontemporal_store(z[ob][nb][i] - lse, &out[(unsigned)l * N + n]);
-            else out[(unsigned)l * N + n] = z[ob][nb][i] - lse;
+            if constexpr (STREAM) __builtin_nontemporal_store(z[nb][j] - lse, &cur.out[(unsigned)l * N + n]);
+            else cur.out[(unsigned)l * N + n] = z[nb][j] - lse;
           }
         }
       }
     }
+    if (!has_next) break;
+    // the staging buffers and the own-row log q are free: every wavefront
+    // passed the barrier above after its last read of them
+    store_region(0, v);
+    __syncthreads();   // chunk 0 of the next tile staged; this tile's red_m / red_s are read
+    i = inext;
+    cur = nxt;
   }
-  (void)mx;
-  (void)se;
+}
+
+// Compute units of the current device (queried once per device).
+inline int compute_units() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
 }
 
 template <int LP, int PREC, bool STREAM>
 hipError_t go(const StepArgs& a, int conn, int compat, hipStream_t s) {
-  const dim3 grid((unsigned)(((a.W + kTN - 1) / kTN) * a.H * a.B)), block(kNT);
+  const long long tiles = (long long)((a.W + kTN - 1) / kTN) * a.H * a.B;
+  // resident workgroups for the whole launch, a multiple of 8 so that each
+  // stays on one XCD's tile range, at most one per tile
+  long long wgs = (long long)Geo<LP>::WG_PER_CU * compute_units();
+  if (tiles <= wgs) wgs = tiles;
+  else wgs -= wgs % lanes::kXcds;
+  const dim3 grid((unsigned)wgs), block(Geo<LP>::NT);
   const float om = (float)(1.0 - (double)a.alpha);
   const int potts = compat == MF_COMPAT_POTTS;
   if (conn == 4) hipLaunchKernelGGL((large_step_kernel<LP, 4, PREC, STREAM>), grid, block, 0, s, a, om, potts);

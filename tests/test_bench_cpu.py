@@ -54,3 +54,51 @@ def test_traffic_used_only_for_current_sources(tmp_path, monkeypatch):
 def test_source_hash_covers_existing_files(kind):
     h = bench.source_hash(kind)
     assert len(h) == 16 and int(h, 16) >= 0
+
+
+def test_roofline_bound_follows_the_counters():
+    g = synth.grid_theta_random(1, 32, 32, 21, synth.GRID8)
+    algo = bench.algorithmic_bytes(g, 4)
+    t = 1e-5
+    # no counters: HBM, with the effective figure
+    r = bench.roofline_object(g, 4, "f32", t, 10, "k", None)
+    assert r["bound"] == "hbm" and r["traffic"] is None
+    assert abs(r["frac"] - algo / t / 1e9 / bench.HBM_PEAK_GBS) < 1e-4
+    # the state stays in the cache and the VALU count is known: VALU issue
+    c = {"hbm_bytes_per_launch": algo // 4, "sq_insts_valu_per_launch": 3.0e6, "rocprof_avg_us": 11.0}
+    r = bench.roofline_object(g, 4, "f32", t, 10, "k", c)
+    assert r["bound"] == "valu_issue" and r["unit"].startswith("G wave64")
+    assert abs(r["frac"] - 3.0e6 / t / 1e9 / bench.VALU_ISSUE_PEAK_G) < 1e-4
+    assert r["hbm"]["traffic_over_algorithmic"] == 0.25
+    assert abs(r["rocprof"]["frac"] - 3.0e6 / 11e-6 / 1e9 / bench.VALU_ISSUE_PEAK_G) < 1e-4
+    # bytes moved close to the algorithmic ones: HBM, whatever the VALU count
+    c = {"hbm_bytes_per_launch": algo, "sq_insts_valu_per_launch": 3.0e6}
+    assert bench.roofline_object(g, 4, "f32", t, 10, "k", c)["bound"] == "hbm"
+
+
+def test_many_label_grids_report_the_matrix_cores():
+    g = synth.grid_theta_random(1, 4, 100, 128, synth.GRID8)
+    fl = bench.mfma_flops_per_launch(g, 1, "f32")
+    nodes = 4 * 128                      # the width rounded up to 64-node tiles
+    assert fl["issued"] == 2.0 * 128 * 128 * nodes and fl["algorithmic"] == 2.0 * 128 * 128 * 400
+    assert bench.mfma_flops_per_launch(g, 1, "bf16")["issued"] == 3 * fl["issued"]
+    r = bench.roofline_object(g, 1, "f32", 1e-6, 10, "k", None)
+    assert "mfma" in r and r["mfma"]["peak"] == bench.MFMA_F32_PEAK_TFLOPS
+    assert r["bound"] in ("hbm", "mfma")
+    assert bench.source_kind(g) == "large"
+    assert bench.mfma_flops_per_launch(synth.workload_c1(), 1, "f32") is None
+
+
+def test_parity_check_against_the_oracle():
+    import numpy as np
+    import oracle as O
+    inst = synth.grid_theta_random(3, 12, 9, 5, synth.GRID8, iters=7)
+    model = O.grid_model(inst.unary[0].astype(np.float64), 12, 9, 8, theta=inst.theta.astype(np.float64))
+    q = np.exp(O.solve(model, inst.alpha, 7)[-1])[None]
+    p = bench.parity_check(inst, q, "f32")
+    assert p["max_abs_dq"] < 1e-12 and p["passed"] and p["argmax_agreement"] == 1.0
+    assert 0 < p["fp32_floor_max_abs_dq"] < 1e-5
+    q2 = q.copy()
+    q2[0, :, 0] = q2[0, ::-1, 0]
+    assert not bench.parity_check(inst, q2, "f32")["passed"]
+    assert bench.parity_check(inst, q, "bf16")["passed"] is None
