@@ -196,8 +196,10 @@ def dense_instance(seed, n_nodes=4096, n_labels=21, pos_high=64.0, alpha=0.5, it
     ``uniform(0, 1, (N, 3))``, co-occurrence matrix via
     :func:`symmetric_zero_diag` on U[0,1], logits
     ``2 * standard_normal((N, L))`` (node-major draw, stored label-major).
-    The kernel matrix itself is *not* built here: each side builds it from
-    the features.
+    The kernel matrix is built from the features by :func:`dense_kernel_bf16`
+    (an input of the solver like the unaries); the library can also build it
+    on the device (``mf_dense_kernel``), which its own tests compare with
+    the oracle's kernel.
     """
     rng = np.random.default_rng(seed)
     pos = rng.uniform(0.0, pos_high, (n_nodes, 2))
@@ -212,6 +214,24 @@ def dense_instance(seed, n_nodes=4096, n_labels=21, pos_high=64.0, alpha=0.5, it
                     n_nodes=n_nodes, unary=u, compat=COMPAT_POTTS, potts_w=float(np.float32(potts_w)),
                     alpha=float(np.float32(alpha)), iters=iters, features=feats,
                     cooc=cooc if with_cooc else None)
+
+
+def dense_kernel_bf16(features):
+    """Bits of the dense CRF's kernel matrix as the solver receives it:
+    K_ij = exp(-|f_i - f_j|^2 / 2) computed in FP64 from the FP32 features,
+    K_ii = 0, rounded to FP32 and then to bfloat16 with ties to even.
+    Returns uint16 [N, N] (row-major)."""
+    f = np.asarray(features, dtype=np.float64)
+    n = f.shape[0]
+    d2 = np.empty((n, n))
+    for r0 in range(0, n, 512):      # squared distances, a block of rows at a time
+        blk = f[r0:r0 + 512, None, :] - f[None, :, :]
+        d2[r0:r0 + 512] = (blk * blk).sum(-1)
+    k = np.exp(-0.5 * d2)
+    np.fill_diagonal(k, 0.0)
+    bits = k.astype(np.float32).view(np.uint32).astype(np.uint64)
+    bits = (bits + 0x7FFF + ((bits >> 16) & 1)) >> 16
+    return np.ascontiguousarray(bits.astype(np.uint16))
 
 
 def workload_c3():

@@ -22,9 +22,22 @@ def oracle_model(inst, b=0, K=None):
     if inst.graph == synth.CSR:
         return O.csr_model(u, inst.row_ptr, inst.col, inst.csr_w, theta=th, potts_w=pw)
     if K is None:
-        K = O.round_to_bf16(O.gaussian_kernel(inst.features))
+        K = dense_K_f64(inst)
     cooc = None if inst.cooc is None else inst.cooc.astype(np.float64)
     return O.dense_model(u, K, potts_w=pw, theta=th, cooc=cooc)
+
+
+def dense_K_f64(inst):
+    """The dense instance's kernel matrix (the input both sides receive), widened to FP64."""
+    bits = synth.dense_kernel_bf16(inst.features)
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def dense_K_device(inst, device="cuda:0"):
+    """The same kernel matrix uploaded as a bfloat16 [N, N] device tensor."""
+    import torch
+    bits = synth.dense_kernel_bf16(inst.features).view(np.int16)
+    return torch.from_numpy(bits).to(device).view(torch.bfloat16)
 
 
 def oracle_lipschitz(inst):
@@ -57,7 +70,7 @@ def gpu_solver(inst, alpha=None, precision="f32", init="unary", device="cuda:0",
                     csr_w=None if inst.csr_w is None else torch.from_numpy(inst.csr_w).to(dev))
     else:
         if "dense_K" not in kw:
-            kw["dense_K"] = mf.dense_kernel(torch.from_numpy(inst.features).to(dev))
+            kw["dense_K"] = dense_K_device(inst, device)
         if inst.cooc is not None:
             args["cooc"] = torch.from_numpy(inst.cooc).to(dev)
     args.update(kw)

@@ -6,9 +6,11 @@ Tolerances, max |q_gpu - q_oracle|:
   step from an identical state; end to end 1e-5 up to t = 10 and twice the
   FP32 rounding floor (the oracle's arithmetic run in FP32) after that;
 * BF16 messages (one plane): 2e-3 per step.
-The kernel matrix is built on the GPU in FP32 and rounded to BF16; the
-oracle builds it in FP64 and rounds it the same way, so the two agree to one
-BF16 unit in the last place (a handful of entries sit on a rounding edge).
+Both sides receive the same BF16 kernel matrix (built by the input
+generator from the features).  The library's own kernel builder
+(mf_dense_kernel, FP32 on the device) is checked separately against the
+oracle's FP64 kernel rounded the same way: they agree to one BF16 unit in
+the last place (a handful of entries sit on a rounding edge).
 """
 import os
 import sys
@@ -37,6 +39,12 @@ def gpu_state(s):
 
 
 def gpu_K(inst):
+    """The instance's kernel matrix, as the input generator builds it, on the device."""
+    return cases.dense_K_device(inst)
+
+
+def built_K(inst):
+    """The kernel matrix built by the library from the features."""
     from paper_1511_06103_amd import mf
     K = mf.dense_kernel(torch.from_numpy(inst.features).to("cuda:0"))
     torch.cuda.synchronize()
@@ -56,7 +64,7 @@ def bf16_ulps(a, b):
 @pytest.mark.parametrize("n", [1, 7, 300, 1024])
 def test_dense_kernel_builder(n):
     inst = synth.dense_instance(60 + n, n, 3)
-    K = K_to_f64(gpu_K(inst))
+    K = K_to_f64(built_K(inst))
     ref = O.round_to_bf16(O.gaussian_kernel(inst.features))
     assert np.all(np.diag(K) == 0)
     d = bf16_ulps(K, ref)
@@ -152,9 +160,9 @@ def test_dense_workload_4096_end_to_end():
         report.append((t, err, fl))
         bound = 1e-5 if t <= 10 else max(1e-5, 2 * fl)
         assert err <= bound, report
-    # the kernel built from the features agrees with the oracle's to one BF16 ulp
+    # the library's kernel builder agrees with the oracle's kernel to one BF16 ulp
     ref_rows = O.round_to_bf16(O.gaussian_kernel(inst.features)[:64])
-    assert bf16_ulps(Kh[:64], ref_rows).max() <= 1
+    assert bf16_ulps(K_to_f64(built_K(inst))[:64], ref_rows).max() <= 1
     print("dense 4096 t, max|dq|, fp32 floor:", report)
 
 

@@ -51,12 +51,8 @@ def _device_lipschitz(inst, iters, seed=7, **kw):
 
 
 def _dense_K(inst):
-    """The device-built BF16 kernel matrix, for both sides (its FP32 exp may
-    round to a neighbouring BF16 value of the FP64 one)."""
-    from paper_1511_06103_amd import mf
-    K = mf.dense_kernel(torch.from_numpy(inst.features).to("cuda:0"))
-    torch.cuda.synchronize()
-    return K, K.float().cpu().numpy().astype(np.float64)
+    """The instance's BF16 kernel matrix (the input generator's), for both sides."""
+    return cases.dense_K_device(inst), cases.dense_K_f64(inst)
 
 
 @pytest.mark.parametrize("which", ["grid8_theta_L21", "grid4_potts_L2", "grid8_theta_L5_batch",

@@ -1,0 +1,17 @@
+"""The seeded input generators: the dense CRF's kernel matrix that both the
+oracle and the library receive equals the oracle's own Gaussian kernel
+(pinned to scipy's distances) rounded to BF16."""
+import numpy as np
+
+import oracle as O
+from paper_1511_06103_amd import synth
+
+
+def test_dense_kernel_input_equals_the_oracle_kernel_rounded():
+    for n, high in ((1, 64.0), (37, 3.0), (600, 64.0)):
+        inst = synth.dense_instance(5 + n, n, 3, pos_high=high)
+        bits = synth.dense_kernel_bf16(inst.features)
+        assert bits.dtype == np.uint16 and bits.shape == (n, n)
+        k = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        np.testing.assert_array_equal(k, O.round_to_bf16(O.gaussian_kernel(inst.features)))
+        assert np.all(np.diag(k) == 0) and np.array_equal(k, k.T)
