@@ -74,6 +74,8 @@ WORKLOADS = {
     "dense4096_L21_cooc": lambda s: s.workload_c3(),
     "csr65536_L21": lambda s: s.csr_instance(8, 65536, 21, avg_degree=8, weighted=True, alpha=0.5, iters=100,
                                              name="csr65536_L21"),
+    # the 2048 x 2048 grid as a general graph: CSR with a grid's locality, beyond the cache
+    "csr_grid2048_L21": lambda s: s.grid_as_csr(s.workload_big()),
 }
 ADJOINT_CKPT = 5
 
@@ -128,9 +130,10 @@ def algorithmic_bytes(inst, k, precision="f32"):
     B, L, N = inst.unary.shape
     if inst.graph == 3:      # dense: the BF16 K stream (2 N^2 B) and the state (12 B per node-label)
         return k * B * (2 * N * N + BYTES_PER_UPDATE * N * L)
-    if inst.graph == 2:      # CSR: log q, u, log q' and the node-major q copy written and gathered
+    if inst.graph == 2:      # CSR: log q, u, log q', the node-major q copy written and gathered, the graph
         qb = 4 if precision == "f32" else 2
-        return k * B * N * L * (BYTES_PER_UPDATE + 2 * qb)
+        graph = 4 * (N + 1) + inst.col.size * (4 + (0 if inst.csr_w is None else 4))
+        return k * (B * N * L * (BYTES_PER_UPDATE + 2 * qb) + graph)
     return BYTES_PER_UPDATE * B * N * L * k
 
 

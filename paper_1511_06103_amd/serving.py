@@ -96,6 +96,7 @@ class ServerStats:
     max_active: int = 0
     max_used_bytes: int = 0
     ticks: int = 0
+    kernel_s: float = 0.0     # device time of the stepping launches (HIP events around each tick)
 
     def summary(self):
         lat = np.array(self.latencies_s) if self.latencies_s else np.array([np.nan])
@@ -104,7 +105,9 @@ class ServerStats:
                 "throughput_updates_per_s": self.updates / self.makespan_s if self.makespan_s > 0 else 0.0,
                 "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-                "max_active": self.max_active, "max_used_bytes": self.max_used_bytes, "ticks": self.ticks}
+                "max_active": self.max_active, "max_used_bytes": self.max_used_bytes, "ticks": self.ticks,
+                "step_kernels_s": self.kernel_s,
+                "staging_and_host_s": self.makespan_s - self.kernel_s}
 
 
 class Server:
@@ -211,6 +214,7 @@ class Server:
         pending = sorted(requests, key=lambda r: r.arrival_s)
         t0 = time.perf_counter()
         tick_events: List[torch.cuda.Event] = []
+        spans: List[tuple] = []
         i = 0
         while i < len(pending) or self.queue or self.active or self.draining:
             now = time.perf_counter() - t0
@@ -223,10 +227,13 @@ class Server:
             if self.active:
                 # each problem advances at its own pace: up to steps_per_tick, never past its count
                 ks = [min(self.steps_per_tick, s.req.iters - s.solver.iteration) for s in self.active]
+                t_a = torch.cuda.Event(enable_timing=True)
+                t_a.record()
                 mf.step_many([s.solver for s in self.active], ks)
                 self.stats.ticks += 1
-                ev = torch.cuda.Event()
+                ev = torch.cuda.Event(enable_timing=True)
                 ev.record()
+                spans.append((t_a, ev))
                 tick_events.append(ev)
                 still = []
                 for s in self.active:
@@ -245,6 +252,8 @@ class Server:
             elif not self.active and not self.queue and i < len(pending):
                 time.sleep(max(0.0, min(0.001, pending[i].arrival_s - (time.perf_counter() - t0))))
         self.stats.makespan_s = time.perf_counter() - t0 - (min(r.arrival_s for r in requests) if requests else 0)
+        torch.cuda.synchronize()
+        self.stats.kernel_s = sum(a.elapsed_time(b) for a, b in spans) * 1e-3
         return self.stats
 
 
@@ -259,19 +268,28 @@ def requests_from_trace(trace, alpha=0.5, iters=100):
     return out
 
 
-def solve_alone(req: SolveRequest, precision="bf16", device="cuda:0") -> np.ndarray:
-    """The plain path: one request, its own solver, one step per launch."""
+def solve_alone(req: SolveRequest, precision="bf16", device="cuda:0", steps_per_launch=1, timing=None) -> np.ndarray:
+    """The plain path: one request, its own solver, one solve.  With
+    steps_per_launch = 1 every step is its own launch (the per-tile
+    arithmetic of the batched kernel, so the results are bitwise the
+    server's); 0 leaves the launch shape to the library (fused steps on
+    small grids).  ``timing`` (a list) collects the device time of the solve."""
     dev = torch.device(device)
     u = torch.from_numpy(req.unary).to(dev)
     th = torch.from_numpy(req.theta).to(dev)
     graph = "grid4" if req.connectivity == 4 else "grid8"
     s = mf.MeanField(u, graph, height=req.height, width=req.width, theta=th, alpha=req.alpha,
-                     precision=precision, steps_per_launch=1)
+                     precision=precision, steps_per_launch=steps_per_launch)
     q = torch.empty_like(u)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
     s.solve(req.iters, q)
-    torch.cuda.synchronize()
+    b.record()
+    out = q.cpu().numpy()     # synchronises
+    if timing is not None:
+        timing.append(a.elapsed_time(b) * 1e-3)
     s.close()
-    return q.cpu().numpy()
+    return out
 
 
 def main(argv=None):
@@ -307,15 +325,22 @@ def main(argv=None):
         srv2 = Server(budget_bytes=args.budget_mib << 20, precision=args.precision, **sched)
         out["saturation_batched"] = srv2.run(reqs2, realtime=False).summary()
         print(json.dumps(out["saturation_batched"]), file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        tot = 0
-        for r in reqs2:
-            solve_alone(r, args.precision)
-            tot += r.updates
-        dt = time.perf_counter() - t
-        out["saturation_one_solve_per_launch"] = {"makespan_s": dt, "throughput_updates_per_s": tot / dt}
-        out["batched_over_alone"] = out["saturation_batched"]["throughput_updates_per_s"] / (tot / dt)
+        tot = sum(r.updates for r in reqs2)
+        for name, spl in (("saturation_alone_one_step_per_launch", 1), ("saturation_alone_library_default", 0)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            dev_s = []
+            for r in reqs2:
+                solve_alone(r, args.precision, steps_per_launch=spl, timing=dev_s)
+            dt = time.perf_counter() - t
+            out[name] = {"makespan_s": dt, "throughput_updates_per_s": tot / dt, "solve_kernels_s": sum(dev_s),
+                         "staging_and_host_s": dt - sum(dev_s)}
+            print(json.dumps({name: out[name]}), file=sys.stderr, flush=True)
+        bt = out["saturation_batched"]["throughput_updates_per_s"]
+        out["batched_over_alone_one_step_per_launch"] = bt / out["saturation_alone_one_step_per_launch"][
+            "throughput_updates_per_s"]
+        out["batched_over_alone_library_default"] = bt / out["saturation_alone_library_default"][
+            "throughput_updates_per_s"]
     print(json.dumps(out), flush=True)
 
 

@@ -295,6 +295,36 @@ def csr_instance(seed, n_nodes, n_labels, avg_degree=6, weighted=True, alpha=0.5
                     iters=iters, row_ptr=row_ptr, col=col, csr_w=w)
 
 
+def grid_csr_graph(height, width, conn=GRID8):
+    """The free-boundary grid of :func:`grid_theta_random` as a CSR graph in
+    raster node order (n = y * width + x), rows sorted, unit weights (none
+    stored): a general graph with the locality of a grid."""
+    ys, xs = np.meshgrid(np.arange(height), np.arange(width), indexing="ij")
+    ys, xs = ys.ravel(), xs.ravel()
+    offs = [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 1), (1, -1), (1, 0), (1, 1)]
+    if conn == GRID4:
+        offs = [(-1, 0), (0, -1), (0, 1), (1, 0)]
+    cols = []
+    valid = []
+    for dy, dx in offs:                       # in this order the columns of a row are sorted
+        yy, xx = ys + dy, xs + dx
+        valid.append((yy >= 0) & (yy < height) & (xx >= 0) & (xx < width))
+        cols.append(yy * width + xx)
+    cols = np.stack(cols, 1)
+    valid = np.stack(valid, 1)
+    row_ptr = np.concatenate([[0], np.cumsum(valid.sum(1))]).astype(np.int32)
+    return row_ptr, np.ascontiguousarray(cols[valid].astype(np.int32))
+
+
+def grid_as_csr(inst):
+    """A grid instance of :func:`grid_theta_random` re-expressed as a CSR
+    instance: the same unaries, Theta and step size on the same graph."""
+    row_ptr, col = grid_csr_graph(inst.height, inst.width, inst.graph)
+    return Instance(name=f"csr_{inst.name}", graph=CSR, n_labels=inst.n_labels, n_nodes=inst.n_nodes,
+                    unary=inst.unary, theta=inst.theta, compat=inst.compat, potts_w=inst.potts_w,
+                    alpha=inst.alpha, iters=inst.iters, row_ptr=row_ptr, col=col, csr_w=None)
+
+
 @dataclass
 class Request:
     index: int

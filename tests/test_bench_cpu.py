@@ -26,9 +26,13 @@ def test_algorithmic_bytes_per_launch():
     g = synth.grid_theta_random(1, 8, 8, 5, synth.GRID8)
     assert bench.algorithmic_bytes(g, 4) == 12 * 64 * 5 * 4
     c = synth.csr_instance(2, 100, 21, 4, True)
-    # log q, u, log q' (4 B each) plus the node-major q written and gathered
-    assert bench.algorithmic_bytes(c, 1) == 100 * 21 * (12 + 8)
-    assert bench.algorithmic_bytes(c, 1, "bf16") == 100 * 21 * (12 + 4)
+    # log q, u, log q' (4 B each), the node-major q written and gathered, and
+    # the graph: row_ptr, col and the weights
+    graph = 4 * 101 + 8 * c.col.size
+    assert bench.algorithmic_bytes(c, 1) == 100 * 21 * (12 + 8) + graph
+    assert bench.algorithmic_bytes(c, 1, "bf16") == 100 * 21 * (12 + 4) + graph
+    g = synth.grid_as_csr(synth.grid_theta_random(1, 6, 9, 5, synth.GRID8))
+    assert bench.algorithmic_bytes(g, 1) == 54 * 5 * 20 + 4 * 55 + 4 * g.col.size     # unweighted
     d = synth.Instance(name="d", graph=synth.DENSE, n_labels=3, n_nodes=50,
                        unary=synth.grid_potts_normal(3, 1, 3, width=50).unary)
     assert bench.algorithmic_bytes(d, 1) == 2 * 50 * 50 + 12 * 50 * 3

@@ -205,3 +205,26 @@ def test_malformed_csr_reported_without_fault(defect):
     with pytest.raises(mf.MFError) as e:
         s.check()
     assert e.value.status == mf.MF_EINVAL
+
+
+def test_csr_grid2048_one_step_sampled_rows():
+    """The 2048 x 2048, L = 21 grid as a CSR graph (the beyond-cache CSR
+    benchmark): one step against the oracle on row bands at the top, the
+    middle and the bottom, the full width."""
+    ginst = synth.workload_big()
+    inst = synth.grid_as_csr(ginst)
+    s = cases.gpu_solver(inst)
+    s.step(1)
+    g = gpu_state(s)[0].reshape(21, 2048, 2048)
+    u = ginst.unary[0].astype(np.float64).reshape(21, 2048, 2048)
+    ell0 = O.init_state(ginst.unary[0].astype(np.float64)).reshape(21, 2048, 2048)
+    th = ginst.theta.astype(np.float64)
+    for y0 in (0, 1023, 2044):
+        lo, hi = max(0, y0 - 1), min(2048, y0 + 5)
+        h = hi - lo
+        sub = O.grid_model(u[:, lo:hi, :].reshape(21, -1), h, 2048, 8, theta=th)
+        ref = O.prox_step(ell0[:, lo:hi, :].reshape(21, -1), sub, ginst.alpha).reshape(21, h, 2048)
+        a = 1 if lo > 0 else 0
+        b = h - 1 if hi < 2048 else h
+        err = cases.max_dq(g[:, lo:hi, :][:, a:b, :].reshape(21, -1), ref[:, a:b, :].reshape(21, -1))
+        assert err <= 1e-6, (y0, err)

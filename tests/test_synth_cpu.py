@@ -15,3 +15,17 @@ def test_dense_kernel_input_equals_the_oracle_kernel_rounded():
         k = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
         np.testing.assert_array_equal(k, O.round_to_bf16(O.gaussian_kernel(inst.features)))
         assert np.all(np.diag(k) == 0) and np.array_equal(k, k.T)
+
+
+def test_grid_as_csr_lists_the_grid_neighbours():
+    for conn, c in ((synth.GRID4, 4), (synth.GRID8, 8)):
+        row_ptr, col = synth.grid_csr_graph(5, 7, conn)
+        rows = [[] for _ in range(35)]
+        for a, b in O.grid_edges(5, 7, c):
+            rows[a].append(b)
+            rows[b].append(a)
+        np.testing.assert_array_equal(row_ptr, np.cumsum([0] + [len(r) for r in rows]))
+        np.testing.assert_array_equal(col, np.concatenate([sorted(r) for r in rows]))
+    g = synth.grid_theta_random(3, 4, 6, 5, synth.GRID8)
+    c = synth.grid_as_csr(g)
+    assert c.graph == synth.CSR and c.csr_w is None and c.unary is g.unary and c.theta is g.theta
