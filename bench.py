@@ -59,6 +59,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 KERNEL_SOURCES = {
     "grid": ("grid_temporal.h", "grid_lanes.h", "msg_codec.h"),
     "large": ("grid_large.hip", "grid_temporal.h", "grid_lanes.h", "msg_codec.h"),
+    "persist": ("grid_persist.hip", "grid_temporal.h", "grid_lanes.h", "msg_codec.h"),
     "csr": ("csr_kernels.hip", "msg_codec.h"),
     "dense": ("dense_kernels.hip",),
 }
@@ -92,9 +93,11 @@ def source_hash(kind="grid"):
     return h.hexdigest()[:16]
 
 
-def source_kind(inst):
+def source_kind(inst, lib_k=None):
     if inst.graph in (0, 1) and inst.n_labels > 32:
         return "large"
+    if inst.graph in (0, 1) and lib_k == PERSIST_STEPS:
+        return "persist"
     return {2: "csr", 3: "dense"}.get(inst.graph, "grid")
 
 
@@ -137,14 +140,15 @@ def algorithmic_bytes(inst, k, precision="f32"):
     return BYTES_PER_UPDATE * B * N * L * k
 
 
-def time_step_launches(solver, torch, launches, warm=1):
+def time_step_launches(solver, torch, launches, warm=1, iters=None):
     """Average duration of one launch of the step kernel as the solve runs it:
-    each mf_step(K) with K = steps fused per launch is exactly one launch.
-    The launches run back to back on the solver's stream between one pair of
-    HIP events, as inside a solve, so the average includes no per-launch
-    event overhead (only the inter-kernel gap of a queued stream)."""
+    each mf_step(K) with K = steps fused per launch (at most the solve's
+    iters) is exactly one launch.  The launches run back to back on the
+    solver's stream between one pair of HIP events, as inside a solve, so
+    the average includes no per-launch event overhead (only the inter-kernel
+    gap of a queued stream)."""
     stream = solver.stream
-    k = solver.steps_per_launch
+    k = solver.steps_per_launch if iters is None else min(solver.steps_per_launch, iters)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     solver.step(k * warm)      # untimed: the first launches touch freshly allocated pages
     torch.cuda.synchronize()
@@ -157,11 +161,17 @@ def time_step_launches(solver, torch, launches, warm=1):
     return a.elapsed_time(b) * 1e-3 / launches, k
 
 
-def step_kernel_name(inst, k):
+PERSIST_STEPS = 4096   # steps per launch the library reports for the persistent grid kernel
+
+
+def step_kernel_name(inst, k, lib_k=None):
     """The kernel one mf_step(k) launches for this workload (the library's
     dispatch rule: a grid of at most 1024 nodes and 8 labels whole in one
-    workgroup, up to 256 steps per launch; otherwise fused steps for k > 1,
-    Theta S on the matrix cores for a general Theta with 8 < L <= 32)."""
+    workgroup, up to 256 steps per launch; a grid with a general Theta,
+    8 < L <= 32 and at most 256 tiles of 16 x 16 in one resident workgroup
+    per tile, the halo exchanged every step; otherwise fused steps for k > 1,
+    Theta S on the matrix cores for a general Theta with 8 < L <= 32).
+    lib_k: the steps per launch the library reports."""
     L, N = inst.unary.shape[1], inst.unary.shape[2]
     if inst.graph == 3:      # one step is the MFMA kernel and the per-node kernel, back to back
         return "mf::dense_step_kernel + mf::dense_epilogue_kernel"
@@ -169,6 +179,8 @@ def step_kernel_name(inst, k):
         return "mf::csr_step_kernel"
     if L > 32:
         return "mf::large::large_step_kernel"
+    if lib_k == PERSIST_STEPS:
+        return "mf::persist::persist_kernel"
     if L <= 8 and N <= 1024 and k > 4:   # the fused kernels take at most 4 steps
         return "mf::whole_grid_kernel"
     if k == 1:
@@ -512,7 +524,7 @@ def main():
         # only the dominant kernel, back to back, timed with HIP events on its
         # stream (the figure to set beside a profiler's average of the same run)
         solver.solve(0)
-        mean_d, k = time_step_launches(solver, torch, args.launches, warm=2)
+        mean_d, k = time_step_launches(solver, torch, args.launches, warm=2, iters=T)
         log(f"kernel mode: {args.launches} launches of {k} steps, {mean_d * 1e6:.2f} us mean per launch "
             f"(HIP events)")
         return
@@ -539,9 +551,10 @@ def main():
     log(f"timed {args.steps} solves: wall {wall * 1e3:.3f} ms, HIP events {ev_total * 1e3:.3f} ms")
 
     # dominant kernel: one step-kernel launch = K steps over all B * N * L node-labels
-    mean_d, k = time_step_launches(solver, torch, args.launches)
-    kname = step_kernel_name(inst, k)
-    counters = load_counters(inst.name, k, source_kind(inst), args.precision)
+    lib_k = solver.steps_per_launch
+    mean_d, k = time_step_launches(solver, torch, args.launches, iters=T)
+    kname = step_kernel_name(inst, k, lib_k)
+    counters = load_counters(inst.name, k, source_kind(inst, lib_k), args.precision)
     roofline = roofline_object(inst, k, args.precision, mean_d, args.launches, kname, counters)
     log(f"{kname} (K={k}): {mean_d * 1e6:.2f} us mean per launch over {args.launches} back-to-back "
         f"launches -> {roofline['hbm']['achieved']:.0f} GB/s algorithmic; bound {roofline['bound']} "

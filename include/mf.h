@@ -138,7 +138,13 @@ typedef struct mf_desc {
                              * blocking); 0 = chosen by the library, 1 = one step per
                              * launch; clamped to what the tile fits in LDS.  With 0, a
                              * grid of at most 1024 nodes and 8 labels is held whole by
-                             * one workgroup and takes up to 256 steps per launch */
+                             * one workgroup and takes up to 256 steps per launch; a
+                             * grid with a general Theta, 8 < L <= 32 and at most 256
+                             * tiles of 16 x 16 (B included) takes up to 4096 steps per
+                             * launch in one resident workgroup per tile, the halo
+                             * exchanged through the workspace after every step, when
+                             * the device keeps all those workgroups resident at once
+                             * (cooperative launch) */
   int32_t rule;            /* mf_rule (MF_RULE_FIXED = 0: the fixed-step proximal update) */
   float rule_gamma1;       /* MOMENTUM / ADAM: decay of the momentum average, in [0, 1) */
   float rule_gamma2;       /* ADAM: decay of the second moment, in [0, 1) */
@@ -215,7 +221,10 @@ mf_status mf_marginals(mf_handle *h, float *q_out);
 
 /* Synchronise the stream and report deferred device errors:
  * MF_ENONFINITE if a non-finite unary (or initial state) was seen, MF_EINVAL
- * for malformed CSR arrays, MF_EDEVICE on a HIP error.  The conditions
+ * for malformed CSR arrays, MF_EDEVICE on a HIP error or when a halo wait of
+ * the persistent grid kernel gave up (its workgroups were not all resident;
+ * the iterates of that launch are invalid; every wait is bounded, so the
+ * launch still ends).  The conditions
  * accumulate over the initialisations since the handle was created or
  * since the last mf_check that reported one; reporting clears them. */
 mf_status mf_check(mf_handle *h);
@@ -333,7 +342,8 @@ mf_status mf_dense_kernel(const float *features, int32_t n, int32_t dim, uint16_
  *    caller's device memory.
  * flags_out: device int32 or NULL; receives the deferred-error bits of this
  *    call (bit 0: a non-finite unary or initial state, bit 1: malformed CSR
- *    arrays), which mf_check would report for a handle.
+ *    arrays, bit 2: a halo wait of the persistent grid kernel gave up),
+ *    which mf_check would report for a handle.
  * Returns MF_ENOWORKSPACE (before any HIP call) when the problem's
  * workspace (mf_workspace_size) exceeds MF_STATIC_SCRATCH_BYTES, and the
  * codes of mf_init otherwise.  Asynchronous on d->stream: nothing is

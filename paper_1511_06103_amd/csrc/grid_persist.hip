@@ -1,0 +1,400 @@
+// Every step of a solve in one launch on a small grid: one resident
+// workgroup per 16 x 16 tile, the one-node halo exchanged through global
+// memory after each step.
+//
+// Step (Eq. 15 with the fixed step of Eq. 16, Sec. 3.1-3.2), per node i:
+//   S_i = sum of q_j over the 4 / 8 grid neighbours (free boundary)
+//   m_i = u_i + Theta S_i
+//   z_i = (1 - alpha) log q_i - alpha m_i;   log q_i <- z_i - lse(z_i)
+// The Jacobi update of Sec. 2.2.2: every node reads its neighbours at the
+// previous iterate.
+//
+// A workgroup of 16 wavefronts owns one tile for the whole launch.  Its
+// log q and unaries stay in registers (wavefront w always updates the same
+// 16 nodes, four lanes per node, Theta S on the FP32 matrix cores with the
+// lane layout of the fused multi-step kernel), q of the tile and of its
+// one-node halo sits in LDS, double-buffered.  Wavefronts 0-3 own the 60
+// nodes of the tile's boundary ring (15 each, the four sides taken as
+// quarter turns of the top row) plus one inner node; wavefronts 4-15 own
+// the other 192 inner nodes, which read only the tile itself and never
+// wait.
+//
+// Halo exchange.  After each step the ring wavefronts publish q of their
+// ring nodes, one 64-bit word per node-label: the step's tag in the high
+// half, the value in the low half, written with an agent-scope atomic store
+// into one of two slots per tile (by step parity).  Before the next step a
+// ring wavefront reads, with agent-scope atomic loads, exactly the halo
+// cells its own nodes' stencils need and re-reads those whose tag is not yet
+// the expected one.  A word is written and read whole, so a matching tag
+// carries its own value: no fence, flag or cache maintenance.  The need is
+// mutual (a halo cell's node has this tile's node in its own stencil), so a
+// producer cannot publish step t + 2 into a slot before every reader of
+// step t in that slot has read it.  Tags are per launch (a base the host
+// advances past every tag it has used), so no word of an earlier launch
+// matches.  Every wait is bounded (20 ms of the constant 100 MHz clock):
+// a wavefront that gives up sets bit 2 of the handle's flags and stops
+// waiting for the rest of the launch, so every workgroup finishes.  The
+// launch is cooperative: the runtime refuses it unless all tiles are
+// resident at once.
+//
+// Arithmetic per node is that of the fused kernel, so the iterates match
+// the fused and one-step paths bitwise (neighbours' q arrive as the exact
+// values their owners computed).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grid_temporal.h"
+#include "mf_internal.h"
+#include "msg_codec.h"
+
+namespace mf {
+namespace persist {
+
+constexpr int kT = 16;                    // tile side
+constexpr int kR = kT + 2;                // region side: the tile and one node either side
+constexpr int kRA = kR * kR;              // region nodes
+constexpr int kRingW = 64;                // exchange words per label plane, slot and tile (60 ring nodes)
+constexpr int kNT = 1024;                 // 16 wavefronts, one 16-node task each
+constexpr long long kWaitTicks = 2000000; // 20 ms at 100 MHz
+
+struct ExchangeArgs {
+  uint64_t* xch;       // [tiles][2][L][kRingW] tagged words
+  unsigned tag0;       // tag of q^0 in this launch; step s publishes tag0 + s
+  int ks;              // steps in this launch
+  int* flags;          // bit 2: a halo wait gave up
+};
+
+// k quarter turns clockwise inside the tile: (y, x) -> (x, 15 - y); also
+// for the halo coordinates -1 and 16.
+__device__ inline void rot(int k, int& y, int& x) {
+  for (int i = 0; i < k; ++i) {
+    const int t = y;
+    y = x;
+    x = kT - 1 - t;
+  }
+}
+
+// Position of a ring node in its tile's exchange plane: the top row
+// (x < 15), the right column (y < 15), the bottom row (x > 0), the left
+// column (y > 0), each 15 nodes in the order of the ring wavefront's lanes.
+__device__ inline int ring_index(int y, int x) {
+  if (y == 0 && x < kT - 1) return x;
+  if (x == kT - 1 && y < kT - 1) return 15 + y;
+  if (y == kT - 1 && x > 0) return 30 + (kT - 1 - x);
+  return 45 + (kT - 1 - y);
+}
+
+template <int LG, int LC, int CONN, int PREC>
+__global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x, float one_minus_alpha) {
+  using M = MsgT<PREC>;
+  using T = typename M::T;
+  constexpr int LP = 4 * LG;
+  constexpr int NOB = (LG + 3) / 4;
+  constexpr int RN = temporal::mfma_plane_stride(kRA);
+  constexpr int NH = CONN == 8 ? 19 : 16;           // halo cells a ring wavefront reads
+  constexpr int NF = (NH * LP + 63) / 64;           // (cell, label) pairs per lane
+  __shared__ T qs[2][LP * RN];
+
+  const int L = LC > 0 ? LC : a.L;
+  const unsigned N = (unsigned)a.N;
+  const int H = a.H, W = a.W;
+  const int tiles_x = (W + kT - 1) / kT, tiles_y = (H + kT - 1) / kT;
+  const int tile = lanes::xcd_tile(blockIdx.x, tiles_x * tiles_y * a.B);
+  const int b = tile / (tiles_x * tiles_y);
+  const int tr = tile - b * (tiles_x * tiles_y);
+  const int tyi = tr / tiles_x, txi = tr - tyi * tiles_x;
+  const size_t base = (size_t)b * L * N;
+  const float* __restrict__ lin = a.state_in + base;
+  const float* __restrict__ ug = a.unary + base;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int col = lane & 15, g = lane >> 4;
+
+  // A operands: Theta[out slot of row col][in slot g + 4 kb], zero outside L x L.
+  float tha[NOB][LG];
+#pragma unroll
+  for (int ob = 0; ob < NOB; ++ob) {
+    const int jo = 4 * ob + (col & 3);
+    const int so = (col >> 2) + 4 * jo;
+#pragma unroll
+    for (int kb = 0; kb < LG; ++kb) {
+      const int si = g + 4 * kb;
+      const bool ok = jo < LG && so < L && si < L;
+      const float t = a.theta[ok ? so * L + si : 0];
+      tha[ob][kb] = ok ? t : 0.f;
+    }
+  }
+
+  // This lane's node: ring wavefronts take the ring (lanes 0-14) and one of
+  // the four last inner nodes (lane 15); the others take 16 inner nodes.
+  int ny = 0, nx = col;
+  if (wave < 4 && col < 15) {
+    rot(wave, ny, nx);
+  } else {
+    const int i = wave < 4 ? 192 + wave : (wave - 4) * 16 + col;
+    ny = 1 + i / 14;
+    nx = 1 + i % 14;
+  }
+  const int gy = tyi * kT + ny, gx = txi * kT + nx;
+  const bool act = gy < H && gx < W;
+  const bool ring = wave < 4 && col < 15 && act;
+  const unsigned n = act ? (unsigned)(gy * W + gx) : 0u;
+  const int cc = (ny + 1) * kR + nx + 1;
+  const int cb = g * RN + cc;                       // plane g at this node
+  bool valid[LG];
+#pragma unroll
+  for (int j = 0; j < LG; ++j) valid[j] = (LC > 0 && 4 * j + 3 < LC) || g + 4 * j < L;
+  uint64_t* __restrict__ my_x = x.xch + (size_t)tile * 2 * L * kRingW + (unsigned)(15 * wave + col);
+
+  // Both q buffers start at zero: off-grid halo cells, nodes past the
+  // grid's edge and padding label slots stay q = 0.
+  for (int f = tid; f < 2 * LP * RN; f += kNT) (&qs[0][0])[f] = M::enc(0.f);
+
+  float ell[LG], uu[LG];
+#pragma unroll
+  for (int j = 0; j < LG; ++j) {
+    const unsigned off = ((unsigned)(valid[j] ? g + 4 * j : L - 1) * N + n) * 4u;
+    ell[j] = temporal::load_at(lin, off);
+    uu[j] = temporal::load_at(ug, off);
+  }
+  __syncthreads();                                  // buffers cleared
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      if (valid[j]) {
+        const T e = M::enc(__expf(ell[j]));
+        qs[0][cb + 4 * j * RN] = e;
+        if (ring) {
+          const uint64_t w = ((uint64_t)x.tag0 << 32) | __float_as_uint(M::dec(e));
+          __hip_atomic_store(my_x + (unsigned)((g + 4 * j) * kRingW), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+  }
+
+  // Halo pairs of a ring wavefront: pair p = lane + 64 it is cell p % NH of
+  // label p / NH.  Cells are quarter turns of the top row's list:
+  // 8 neighbours: (-1, -1 .. 15), (0, -1), (1, -1); 4 neighbours:
+  // (-1, 0 .. 14), (0, -1).  Off-grid cells are not read (q = 0).
+  unsigned woff[NF], loff[NF];
+  unsigned fetch = 0;
+  if (wave < 4) {
+#pragma unroll
+    for (int it = 0; it < NF; ++it) {
+      const int p = lane + 64 * it;
+      const int c = p % NH, l = p / NH;
+      int hy, hx;
+      if (CONN == 8) {
+        hy = c < 17 ? -1 : c - 17;
+        hx = c < 17 ? c - 1 : -1;
+      } else {
+        hy = c < 15 ? -1 : 0;
+        hx = c < 15 ? c : -1;
+      }
+      rot(wave, hy, hx);
+      const int ghy = tyi * kT + hy, ghx = txi * kT + hx;
+      const bool on = l < L && ghy >= 0 && ghy < H && ghx >= 0 && ghx < W;
+      const int ptile = on ? (b * tiles_y + (ghy >> 4)) * tiles_x + (ghx >> 4) : 0;
+      const int r = on ? ring_index(ghy & (kT - 1), ghx & (kT - 1)) : 0;
+      woff[it] = ((unsigned)ptile * 2u * (unsigned)L + (unsigned)(on ? l : 0)) * kRingW + (unsigned)r;
+      loff[it] = (unsigned)((on ? l : 0) * RN + (hy + 1) * kR + hx + 1);
+      fetch |= on ? 1u << it : 0u;
+    }
+  }
+  __syncthreads();                                  // q^0 of the tile in LDS
+
+  bool aborted = false;
+  for (int s = 0; s < x.ks; ++s) {
+    const int cur = s & 1;
+    T* __restrict__ qc = qs[cur];
+    T* __restrict__ qn = qs[cur ^ 1];
+    if (wave < 4) {
+      // the halo of step s: words of slot s % 2 tagged tag0 + s
+      const unsigned expect = x.tag0 + (unsigned)s;
+      const unsigned slot = (unsigned)(cur * L * kRingW);
+      unsigned pend = fetch;
+      const long long t0 = wall_clock64();
+      while (true) {
+        uint64_t w[NF];
+#pragma unroll
+        for (int it = 0; it < NF; ++it)
+          if ((pend >> it) & 1u)
+            w[it] = __hip_atomic_load(x.xch + woff[it] + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int it = 0; it < NF; ++it) {
+          if (((pend >> it) & 1u) && (unsigned)(w[it] >> 32) == expect) {
+            qc[loff[it]] = M::enc(__uint_as_float((unsigned)w[it]));
+            pend &= ~(1u << it);
+          }
+        }
+        if (!__any(pend != 0u)) break;
+        if (aborted || wall_clock64() - t0 > kWaitTicks) {
+          if (!aborted && lane == 0) atomicOr(x.flags, 4);
+          aborted = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      // this wavefront's LDS writes above come before its reads below
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+
+    // LDS byte address of plane g at region offset - kR - 1 of this node
+    const unsigned qb = temporal::lds_addr(qc) + (unsigned)(cb - kR - 1) * (unsigned)sizeof(T);
+    float S[LG];
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      const T* qp = temporal::lds_ptr<T>(temporal::opaque(qb + (unsigned)(4 * j * RN) * (unsigned)sizeof(T)));
+      const float n0 = M::dec(qp[1]), w0 = M::dec(qp[kR]), e0 = M::dec(qp[kR + 2]), s0 = M::dec(qp[2 * kR + 1]);
+      float tot = (n0 + w0) + (e0 + s0);
+      if (CONN == 8) tot += (M::dec(qp[0]) + M::dec(qp[2])) + (M::dec(qp[2 * kR]) + M::dec(qp[2 * kR + 2]));
+      S[j] = valid[j] ? tot : 0.f;
+    }
+
+    temporal::f32x4 acc[NOB];
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob) acc[ob] = temporal::f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < LG; ++kb) {
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob)
+        acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tha[ob][kb], S[kb], acc[ob], 0, 0, 0);
+    }
+
+    float z[LG];
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      const float zz = one_minus_alpha * ell[j] - a.alpha * (uu[j] + acc[j >> 2][j & 3]);
+      z[j] = valid[j] ? zz : -INFINITY;
+    }
+    float mx = z[0];
+#pragma unroll
+    for (int j = 1; j < LG; ++j) mx = fmaxf(mx, z[j]);
+    mx = temporal::rows_max(mx);
+    float e[LG];
+#pragma unroll
+    for (int j = 0; j < LG; ++j) e[j] = __expf(z[j] - mx);   // exp(-inf) = 0 for empty slots
+    float se = e[0];
+#pragma unroll
+    for (int j = 1; j < LG; ++j) se += e[j];
+    se = temporal::rows_sum(se);
+    const float lse = mx + __logf(se);
+    const float inv = __builtin_amdgcn_rcpf(se);   // 1 ulp; se >= 1 (the max term is exp(0))
+    const unsigned tag = x.tag0 + (unsigned)s + 1u;
+    const unsigned nslot = (unsigned)((cur ^ 1) * L * kRingW);
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      ell[j] = z[j] - lse;
+      if (act && valid[j]) {
+        const T qv = M::enc(e[j] * inv);
+        qn[cb + 4 * j * RN] = qv;
+        if (ring) {
+          const uint64_t w = ((uint64_t)tag << 32) | __float_as_uint(M::dec(qv));
+          __hip_atomic_store(my_x + nslot + (unsigned)((g + 4 * j) * kRingW), w, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // log q of the last step
+  float* __restrict__ out = a.state_out + base;
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < LG; ++j)
+      if (valid[j]) out[(unsigned)(g + 4 * j) * N + n] = ell[j];
+  }
+}
+
+// Workgroups of one instantiation resident per compute unit (queried once
+// per device).
+template <int LG, int LC, int CONN, int PREC>
+int resident_per_cu() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persist_kernel<LG, LC, CONN, PREC>, kNT, 0) != hipSuccess)
+      n = 0;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) coop = 0;
+    cached[dev] = coop ? n * cus : 0;
+    if (cached[dev] == 0) cached[dev] = -1;
+  }
+  return cached[dev] > 0 ? cached[dev] : 0;
+}
+
+template <int LG, int LC, int CONN, int PREC>
+hipError_t go(const StepArgs& a, const ExchangeArgs& x, hipStream_t s, bool query, int* capacity) {
+  if (query) {
+    *capacity = resident_per_cu<LG, LC, CONN, PREC>();
+    return hipSuccess;
+  }
+  const int tiles = ((a.W + kT - 1) / kT) * ((a.H + kT - 1) / kT) * a.B;
+  StepArgs aa = a;
+  ExchangeArgs xx = x;
+  float om = (float)(1.0 - (double)a.alpha);
+  void* args[] = {&aa, &xx, &om};
+  return hipLaunchCooperativeKernel((const void*)persist_kernel<LG, LC, CONN, PREC>, dim3(tiles), dim3(kNT), args, 0, s);
+}
+
+template <int PREC>
+hipError_t by_labels(const StepArgs& a, int conn, const ExchangeArgs& x, hipStream_t s, bool query, int* cap) {
+  const int L = a.L;
+  if (conn == 4) {
+    if (L <= 16) return go<4, 0, 4, PREC>(a, x, s, query, cap);
+    if (L == 21) return go<6, 21, 4, PREC>(a, x, s, query, cap);
+    if (L <= 24) return go<6, 0, 4, PREC>(a, x, s, query, cap);
+    return go<8, 0, 4, PREC>(a, x, s, query, cap);
+  }
+  if (L <= 16) return go<4, 0, 8, PREC>(a, x, s, query, cap);
+  if (L == 21) return go<6, 21, 8, PREC>(a, x, s, query, cap);
+  if (L <= 24) return go<6, 0, 8, PREC>(a, x, s, query, cap);
+  return go<8, 0, 8, PREC>(a, x, s, query, cap);
+}
+
+hipError_t dispatch(const StepArgs& a, int conn, int precision, const ExchangeArgs& x, hipStream_t s, bool query,
+                    int* cap) {
+  switch (precision) {
+    case MF_P_F32: return by_labels<P_F32>(a, conn, x, s, query, cap);
+    case MF_P_BF16MSG: return by_labels<P_BF16>(a, conn, x, s, query, cap);
+    default: return by_labels<P_F16>(a, conn, x, s, query, cap);
+  }
+}
+
+}  // namespace persist
+
+bool grid_persist_eligible(int L, int compat) { return compat == MF_COMPAT_GENERAL && L > 8 && L <= 32; }
+
+size_t grid_persist_exchange_bytes(int B, int H, int W, int L) {
+  const size_t tiles = (size_t)B * ((W + persist::kT - 1) / persist::kT) * ((H + persist::kT - 1) / persist::kT);
+  return tiles * 2 * (size_t)L * persist::kRingW * sizeof(uint64_t);
+}
+
+int grid_persist_capacity(int L, int conn, int precision) {
+  StepArgs a{};
+  a.L = L;
+  persist::ExchangeArgs x{};
+  int cap = 0;
+  persist::dispatch(a, conn, precision, x, nullptr, true, &cap);
+  return cap;
+}
+
+hipError_t launch_grid_persist(const StepArgs& a, int conn, int precision, uint64_t* xch, unsigned tag0, int ks,
+                               int* flags, hipStream_t s) {
+  persist::ExchangeArgs x;
+  x.xch = xch;
+  x.tag0 = tag0;
+  x.ks = ks;
+  x.flags = flags;
+  int cap = 0;
+  return persist::dispatch(a, conn, precision, x, s, false, &cap);
+}
+
+}  // namespace mf

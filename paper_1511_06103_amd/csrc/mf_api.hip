@@ -23,6 +23,8 @@ struct mf_handle {
   int iter = 0;     // steps since (re)initialisation
   int k_launch = 1; // steps fused per launch
   bool whole = false;  // the whole grid in one workgroup, every step of a launch in LDS
+  bool persist = false;  // one resident workgroup per tile, the halo exchanged each step
+  unsigned xtag = 1;     // first unused exchange tag (the exchange area starts zeroed)
   std::string err;
 };
 
@@ -39,6 +41,20 @@ mf_status fail(mf_handle* h, mf_status st, const std::string& msg) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool is_grid(int g) { return g == MF_GRID4 || g == MF_GRID8; }
+
+bool choose_whole_grid(const mf_desc& d);
+hipError_t clear_exchange(mf_handle* h);
+
+// Grids the persistent kernel may take (whether the device keeps every tile
+// resident is checked when the handle is created): library-chosen launch
+// shapes, the fixed step, general Theta with 8 < L <= 32, at most
+// kPersistMaxTiles 16 x 16 tiles.
+bool persist_possible(const mf_desc& d) {
+  if (!is_grid(d.graph) || d.rule != MF_RULE_FIXED || d.steps_per_launch > 0 || choose_whole_grid(d)) return false;
+  if (!mf::grid_persist_eligible(d.n_labels, d.compat) || d.height < 1 || d.width < 1) return false;
+  const int64_t tiles = (int64_t)d.batch * ((d.width + 15) / 16) * ((d.height + 15) / 16);
+  return tiles <= mf::kPersistMaxTiles;
+}
 
 mf::WorkspaceLayout layout_for(const mf_desc& d) {
   mf::WorkspaceLayout w;
@@ -76,6 +92,11 @@ mf::WorkspaceLayout layout_for(const mf_desc& d) {
     const size_t E = (size_t)d.batch * d.n_labels * d.n_nodes;
     w.rule_state = off;
     off += align256(sizeof(float) * E * (d.rule == MF_RULE_ADAM ? 2 : 1));
+  }
+  if (persist_possible(d)) {
+    w.xch = off;
+    w.xch_bytes = mf::grid_persist_exchange_bytes(d.batch, d.height, d.width, d.n_labels);
+    off += align256(w.xch_bytes);
   }
   w.total = off;
   return w;
@@ -259,6 +280,11 @@ mf_status enqueue_init(mf_handle* h, bool clear_flags) {
   if (clear_flags) {
     e = mf::launch_clear_flags(flags_ptr(h), 64, h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
+    if (h->persist) {
+      // no tag of the exchange area's earlier contents may match a tag of this handle
+      e = clear_exchange(h);
+      if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("exchange clear: ") + hipGetErrorString(e));
+    }
   }
   if (d.graph == MF_CSR) {
     e = mf::launch_csr_check(d.csr_row_ptr, d.csr_col, d.n_nodes, d.csr_nnz, flags_ptr(h), h->stream);
@@ -382,6 +408,25 @@ mf_status enqueue_steps(mf_handle* h, int n) {
   if (d.graph == MF_CSR) return enqueue_csr_steps(h, n);
   if (d.graph == MF_DENSE) return enqueue_dense_steps(h, n);
   if (d.rule != MF_RULE_FIXED) return enqueue_rule_steps(h, n);
+  if (h->persist) {
+    const int conn = d.graph == MF_GRID4 ? 4 : 8;
+    uint64_t* xch = (uint64_t*)ws_at(h, h->ws.xch);
+    while (n > 0) {
+      const int ks = n < h->k_launch ? n : h->k_launch;
+      hipError_t e = hipSuccess;
+      // a launch uses tags xtag .. xtag + ks; past 2^32 the area is cleared and they restart at 1
+      if (h->xtag > 0xFFFFFFFFu - (unsigned)ks - 1u) e = clear_exchange(h);
+      if (e == hipSuccess)
+        e = mf::launch_grid_persist(grid_args(h, h->cur), conn, d.precision, xch, h->xtag, ks, flags_ptr(h),
+                                    h->stream);
+      if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+      h->xtag += (unsigned)ks + 1u;
+      h->cur ^= 1;
+      h->iter += ks;
+      n -= ks;
+    }
+    return MF_OK;
+  }
   while (n > 0) {
     const int ks = n < h->k_launch ? n : h->k_launch;
     mf::StepArgs a;
@@ -534,6 +579,20 @@ void* scratch_address(hipError_t* err) {
   return g_scratch_ptr[dev];
 }
 
+// The persistent kernel when the device keeps every tile's workgroup
+// resident at once (cooperative launch): no halo recomputation and one
+// launch per kPersistMaxSteps steps.
+bool choose_persist(const mf_desc& d) {
+  if (!persist_possible(d)) return false;
+  const int64_t tiles = (int64_t)d.batch * ((d.width + 15) / 16) * ((d.height + 15) / 16);
+  return tiles <= mf::grid_persist_capacity(d.n_labels, d.graph == MF_GRID4 ? 4 : 8, d.precision);
+}
+
+hipError_t clear_exchange(mf_handle* h) {
+  h->xtag = 1;
+  return mf::launch_fill_f32((float*)ws_at(h, h->ws.xch), h->ws.xch_bytes / sizeof(float), 0.f, h->stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -567,6 +626,8 @@ mf_status mf_init(const mf_desc* d, mf_handle** out) {
   h->ws = layout_for(*d);
   h->k_launch = choose_steps_per_launch(*d);
   h->whole = choose_whole_grid(*d);
+  h->persist = choose_persist(*d);
+  if (h->persist) h->k_launch = mf::kPersistMaxSteps;
   const mf_status s2 = enqueue_init(h, true);
   if (s2 != MF_OK) {
     g_err = h->err;
@@ -621,6 +682,8 @@ mf_status mf_check(mf_handle* h) {
     e = mf::launch_clear_flags(flags_ptr(h), 64, h->stream);
     if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
   }
+  if (flag & 4) return fail(h, MF_EDEVICE, "a halo exchange wait of the persistent grid kernel gave up "
+                                          "(its workgroups were not all resident); the iterates are invalid");
   if (flag & 2) return fail(h, MF_EINVAL, "malformed CSR arrays (row_ptr not monotone from 0 to nnz, "
                                          "or a column index out of range)");
   if (flag & 1) return fail(h, MF_ENONFINITE, "non-finite unary or initial state");
@@ -989,8 +1052,12 @@ mf_status mf_solve_static(const mf_desc* d, int32_t iters, float* q_out, double*
   h.ws = layout_for(dd);
   h.k_launch = choose_steps_per_launch(dd);
   h.whole = choose_whole_grid(dd);
-  // the scratch keeps the previous call's contents: the flags start at zero
+  h.persist = choose_persist(dd);
+  if (h.persist) h.k_launch = mf::kPersistMaxSteps;
+  // the scratch keeps the previous call's contents: the flags start at zero,
+  // and the exchange area holds no tag of this call
   e = mf::launch_clear_flags(flags_ptr(&h), 64, h.stream);
+  if (e == hipSuccess && h.persist) e = clear_exchange(&h);
   if (e != hipSuccess) return fail(nullptr, MF_EDEVICE, std::string("flag clear: ") + hipGetErrorString(e));
   mf_status s2 = solve_impl(&h, iters, q_out);
   if (s2 == MF_OK && F_out) s2 = enqueue_free_energy(&h, F_out);

@@ -172,6 +172,8 @@ struct WorkspaceLayout {
   size_t dt = 0;           // float[2][B][NRB][32] column sums
   size_t dqd = 0;          // double[B][N][L] free-energy scratch
   size_t rule_state = 0;   // float[1 or 2][B][L][N] momentum / ADAM state
+  size_t xch = 0;          // uint64[tiles][2][L][64] halo exchange of the persistent grid kernel
+  size_t xch_bytes = 0;
   DenseGeometry dg;
   int dense_ns = 0;
   size_t total = 0;
@@ -247,5 +249,19 @@ hipError_t launch_grid_step_large(const StepArgs& a, int conn, int compat, int p
 hipError_t launch_grid_step_lanes_many(const ManyArgs& m, int L, int conn, int compat, int prec, hipStream_t s);
 
 int grid_blocks_per_item(int H, int W);
+
+// Every step of a launch in one resident workgroup per 16 x 16 tile, the
+// halo exchanged through tagged words (grid_persist.hip): general Theta,
+// 8 < L <= kSmallLabels, at most kPersistMaxTiles tiles and no more than the
+// device keeps resident (grid_persist_capacity; 0 without cooperative
+// launch).  Steps per launch at most kPersistMaxSteps.  Bit 2 of flags: a
+// halo wait gave up.
+constexpr int kPersistMaxTiles = 256;
+constexpr int kPersistMaxSteps = 4096;
+bool grid_persist_eligible(int L, int compat);
+size_t grid_persist_exchange_bytes(int B, int H, int W, int L);
+int grid_persist_capacity(int L, int conn, int precision);
+hipError_t launch_grid_persist(const StepArgs& a, int conn, int precision, uint64_t* xch, unsigned tag0, int ks,
+                               int* flags, hipStream_t s);
 
 }  // namespace mf

@@ -179,10 +179,26 @@ def test_csr_descriptor_validation():
 
 
 def test_csr_workspace_holds_node_major_q():
-    g = mf.lib().mf_workspace_size(ctypes.byref(good_desc()))
+    g = mf.lib().mf_workspace_size(ctypes.byref(good_desc(steps_per_launch=1)))
     c = mf.lib().mf_workspace_size(ctypes.byref(csr_desc()))
     # two node-major copies of q, L = 21 padded to 24
     assert c - g >= 2 * 64 * 64 * 24 * 4
+
+
+def test_workspace_holds_halo_exchange_of_small_theta_grids():
+    """Grids the persistent kernel may take (library-chosen launch shape,
+    general Theta, 8 < L <= 32, at most 256 tiles of 16 x 16) carry its
+    exchange area: two slots of 64 tagged 8-byte words per label and tile."""
+    def ws(**kw):
+        return mf.lib().mf_workspace_size(ctypes.byref(good_desc(**kw)))
+    base = ws(steps_per_launch=1)
+    assert ws() - base == 16 * 2 * 21 * 64 * 8                        # 64 x 64: 16 tiles
+    big = dict(n_nodes=256 * 256, height=256, width=256)
+    assert ws(**big) - ws(steps_per_launch=4, **big) == 256 * 2 * 21 * 64 * 8
+    for kw in (dict(n_labels=8), dict(compat=mf.COMPAT_POTTS), dict(steps_per_launch=3),
+               dict(n_nodes=257 * 256, height=257, width=256)):      # 272 tiles
+        d = dict(big if "n_nodes" not in kw else {}, **kw)
+        assert ws(**d) == ws(**dict(d, steps_per_launch=1)), kw
 
 
 def test_admissible_alpha_rule():
@@ -210,7 +226,7 @@ def test_step_rule_validation():
     assert validate(good_desc(**{**adam, "rule_v0": -1.0})) == mf.MF_EINVAL
     assert validate(good_desc(rule=mf.RULES["sweep"])) == mf.MF_OK
     E = 64 * 64 * 21 * 4
-    base = mf.lib().mf_workspace_size(ctypes.byref(good_desc()))
+    base = mf.lib().mf_workspace_size(ctypes.byref(good_desc(steps_per_launch=1)))
     mom = mf.lib().mf_workspace_size(ctypes.byref(good_desc(rule=mf.RULES["momentum"], rule_gamma1=0.95)))
     ad = mf.lib().mf_workspace_size(ctypes.byref(good_desc(**adam)))
     assert mom >= base + E and ad >= base + 2 * E
