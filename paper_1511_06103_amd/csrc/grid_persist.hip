@@ -37,9 +37,11 @@
 // launch is cooperative: the runtime refuses it unless all tiles are
 // resident at once.
 //
-// Arithmetic per node is that of the fused kernel, so the iterates match
-// the fused and one-step paths bitwise (neighbours' q arrive as the exact
-// values their owners computed).
+// Arithmetic per node is that of the fused kernel, so with the same launch
+// boundaries the iterates match the fused kernel's bitwise (neighbours' q
+// arrive as the exact values their owners computed).  A launch may also
+// take the initialisation and the write-out of q, with the arithmetic of
+// the separate kernels, so that a solve is one launch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -61,7 +63,9 @@ struct ExchangeArgs {
   uint64_t* xch;       // [tiles][2][L][kRingW] tagged words
   unsigned tag0;       // tag of q^0 in this launch; step s publishes tag0 + s
   int ks;              // steps in this launch
-  int* flags;          // bit 2: a halo wait gave up
+  int* flags;          // bit 0: a non-finite input (with init >= 0); bit 2: a halo wait gave up
+  int init;            // mf_init_mode applied to the state first, or -1 (the state is initialised)
+  float* q_out;        // [B][L][N] q = exp(log q) of the last step, or nullptr
 };
 
 // k quarter turns clockwise inside the tile: (y, x) -> (x, 15 - y); also
@@ -157,6 +161,41 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
     const unsigned off = ((unsigned)(valid[j] ? g + 4 * j : L - 1) * N + n) * 4u;
     ell[j] = temporal::load_at(lin, off);
     uu[j] = temporal::load_at(ug, off);
+  }
+  if (x.init >= 0) {
+    // log q^0 as the initialisation kernel forms it (Eq. 6 reading
+    // q^0 = softmax(-u), or uniform, or the given state): its four label
+    // groups of LG consecutive labels, each summed in order, combined as
+    // (s0 + s2) + (s1 + s3); every lane of a node forms the whole sum
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      if (valid[j]) bad |= !isfinite(uu[j]);
+      if (valid[j] && x.init == MF_INIT_STATE) bad |= !isfinite(ell[j]);
+    }
+    if (x.init == MF_INIT_UNARY) {
+      const unsigned nb = n * 4u;
+      float mx = -INFINITY;
+      for (int l = 0; l < L; ++l) mx = fmaxf(mx, -temporal::load_at(ug, (unsigned)l * N * 4u + nb));
+      float sg[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        sg[k] = 0.f;
+#pragma unroll
+        for (int j = 0; j < LG; ++j) {
+          const int l = k * LG + j;
+          sg[k] += l < L ? expf(-temporal::load_at(ug, (unsigned)(l < L ? l : 0) * N * 4u + nb) - mx) : 0.f;
+        }
+      }
+      const float lse = mx + logf((sg[0] + sg[2]) + (sg[1] + sg[3]));
+#pragma unroll
+      for (int j = 0; j < LG; ++j) ell[j] = -uu[j] - lse;
+    } else if (x.init == MF_INIT_UNIFORM) {
+      const float u0 = -logf((float)a.L);   // the run-time count: the initialisation kernel's device logf
+#pragma unroll
+      for (int j = 0; j < LG; ++j) ell[j] = u0;
+    }
+    if (act && bad) atomicOr(x.flags, 1);
   }
   __syncthreads();                                  // buffers cleared
   if (act) {
@@ -300,12 +339,16 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
     __syncthreads();
   }
 
-  // log q of the last step
+  // log q of the last step, and q as the separate write-out forms it
   float* __restrict__ out = a.state_out + base;
   if (act) {
 #pragma unroll
-    for (int j = 0; j < LG; ++j)
-      if (valid[j]) out[(unsigned)(g + 4 * j) * N + n] = ell[j];
+    for (int j = 0; j < LG; ++j) {
+      if (valid[j]) {
+        out[(unsigned)(g + 4 * j) * N + n] = ell[j];
+        if (x.q_out) x.q_out[base + (size_t)(g + 4 * j) * N + n] = expf(ell[j]);
+      }
+    }
   }
 }
 
@@ -387,12 +430,14 @@ int grid_persist_capacity(int L, int conn, int precision) {
 }
 
 hipError_t launch_grid_persist(const StepArgs& a, int conn, int precision, uint64_t* xch, unsigned tag0, int ks,
-                               int* flags, hipStream_t s) {
+                               int* flags, int init, float* q_out, hipStream_t s) {
   persist::ExchangeArgs x;
   x.xch = xch;
   x.tag0 = tag0;
   x.ks = ks;
   x.flags = flags;
+  x.init = init;
+  x.q_out = q_out;
   int cap = 0;
   return persist::dispatch(a, conn, precision, x, s, false, &cap);
 }

@@ -417,8 +417,8 @@ mf_status enqueue_steps(mf_handle* h, int n) {
       // a launch uses tags xtag .. xtag + ks; past 2^32 the area is cleared and they restart at 1
       if (h->xtag > 0xFFFFFFFFu - (unsigned)ks - 1u) e = clear_exchange(h);
       if (e == hipSuccess)
-        e = mf::launch_grid_persist(grid_args(h, h->cur), conn, d.precision, xch, h->xtag, ks, flags_ptr(h),
-                                    h->stream);
+        e = mf::launch_grid_persist(grid_args(h, h->cur), conn, d.precision, xch, h->xtag, ks, flags_ptr(h), -1,
+                                    nullptr, h->stream);
       if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
       h->xtag += (unsigned)ks + 1u;
       h->cur ^= 1;
@@ -471,6 +471,30 @@ mf_status solve_impl(mf_handle* h, int iters, float* q_out) {
       hipError_t e = mf::launch_grid_whole(a, conn, d.compat, d.precision, ks, first ? d.init : -1, flags_ptr(h),
                                            n == ks ? q_out : nullptr, h->stream);
       if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+      h->cur ^= 1;
+      h->iter += ks;
+      n -= ks;
+    }
+    return MF_OK;
+  }
+  if (h->persist && iters > 0) {
+    // the persistent kernel: the initialisation, the steps and the write-out
+    // of q in one launch per kPersistMaxSteps steps, with the arithmetic of
+    // the separate kernels
+    const mf_desc& d = h->d;
+    const int conn = d.graph == MF_GRID4 ? 4 : 8;
+    uint64_t* xch = (uint64_t*)ws_at(h, h->ws.xch);
+    h->cur = 0;
+    h->iter = 0;
+    for (int n = iters, first = 1; n > 0; first = 0) {
+      const int ks = n < h->k_launch ? n : h->k_launch;
+      hipError_t e = hipSuccess;
+      if (h->xtag > 0xFFFFFFFFu - (unsigned)ks - 1u) e = clear_exchange(h);
+      if (e == hipSuccess)
+        e = mf::launch_grid_persist(grid_args(h, h->cur), conn, d.precision, xch, h->xtag, ks, flags_ptr(h),
+                                    first ? d.init : -1, n == ks ? q_out : nullptr, h->stream);
+      if (e != hipSuccess) return fail(h, MF_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+      h->xtag += (unsigned)ks + 1u;
       h->cur ^= 1;
       h->iter += ks;
       n -= ks;

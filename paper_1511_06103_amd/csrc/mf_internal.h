@@ -261,7 +261,10 @@ constexpr int kPersistMaxSteps = 4096;
 bool grid_persist_eligible(int L, int compat);
 size_t grid_persist_exchange_bytes(int B, int H, int W, int L);
 int grid_persist_capacity(int L, int conn, int precision);
+// init >= 0: the launch starts with the initialisation of that mf_init_mode
+// (flags bit 0 on a non-finite input); q_out != nullptr: it ends by writing
+// q = exp(log q) of the last step.
 hipError_t launch_grid_persist(const StepArgs& a, int conn, int precision, uint64_t* xch, unsigned tag0, int ks,
-                               int* flags, hipStream_t s);
+                               int* flags, int init, float* q_out, hipStream_t s);
 
 }  // namespace mf

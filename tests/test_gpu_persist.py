@@ -144,3 +144,43 @@ def test_message_precisions_against_oracle(precision, tol):
     s.step(3)
     ref = O.solve(cases.oracle_model(inst), 0.5, 3)[-1]
     assert cases.max_dq(state(s)[0].astype(np.float64), ref) <= 3 * tol
+
+
+@pytest.mark.parametrize("init", ["unary", "uniform", "state"])
+def test_solve_in_one_launch_matches_separate_kernels(c2, init):
+    """solve() runs the initialisation, the steps and the write-out of q in
+    one launch; mf_init's initialisation kernel, one launch of the same steps
+    and the separate write-out give the same bits (Eq. 6 reading of q^0)."""
+    B, L, N = c2.unary.shape
+    st = None
+    if init == "state":
+        st = torch.empty((2, B, L, N), dtype=torch.float32, device="cuda:0")
+        g = np.random.default_rng(5).standard_normal((B, L, N)).astype(np.float32)
+        st[0].copy_(torch.from_numpy(g - np.log(np.exp(g).sum(1, keepdims=True))))
+    kw = {} if st is None else {"state": st.clone()}
+    a = cases.gpu_solver(c2, init=init, **kw)
+    qa = torch.empty_like(a.unary)
+    a.solve(7, qa)
+    kw = {} if st is None else {"state": st.clone()}
+    b = cases.gpu_solver(c2, init=init, **kw)
+    b.step(7)
+    qb = b.marginals()
+    torch.cuda.synchronize()
+    assert np.array_equal(state(a), state(b))
+    assert torch.equal(qa, qb)
+    assert a.check() is None and b.check() is None
+
+
+def test_non_finite_unary_reported_by_the_one_launch_solve():
+    inst = synth.grid_theta_random(9, 40, 40, 21, synth.GRID8, iters=3)
+    inst.unary[0, 3, 77] = np.nan
+    from paper_1511_06103_amd import mf
+    s = cases.gpu_solver(inst)
+    assert s.steps_per_launch == PERSIST_STEPS
+    with pytest.raises(mf.MFError) as e:      # mf_init's own initialisation reports it first
+        s.check()
+    assert e.value.status == mf.MF_ENONFINITE
+    s.solve(3)                                # reporting cleared it: this one comes from the solve's launch
+    with pytest.raises(mf.MFError) as e:
+        s.check()
+    assert e.value.status == mf.MF_ENONFINITE
