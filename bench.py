@@ -397,7 +397,17 @@ def roofline_object(inst, k, precision, mean_d, launches, kname, counters):
     # cache (then VALU issue, when counted), or the matrix cores run at a
     # larger fraction of their peak
     cache_resident = traffic is not None and traffic < 0.5 * algo
-    if cache_resident and "valu" in out:
+    if kname == "mf::persist::persist_kernel":
+        # neither HBM nor an issue rate limits it: each step waits for the
+        # neighbours' halo (about 2.1 us from their stores to the matching
+        # loads) and then runs the ring wavefront's task; the fraction is the
+        # effective one, algorithmic bytes over the launch time
+        out["note"] = ("bound by the inter-workgroup halo exchange (latency per step), not by a peak: "
+                       "the state stays in the last-level cache; frac is the effective HBM fraction "
+                       "(algorithmic bytes over the launch time)")
+        if "rocprof" in out:
+            out["rocprof"]["frac"] = out["rocprof"]["hbm_frac"]
+    elif cache_resident and "valu" in out:
         v = out["valu"]
         out.update(bound="valu_issue", achieved=v["achieved"], peak=v["peak"], unit=v["unit"], frac=v["frac"])
         if "rocprof" in out:
@@ -407,7 +417,7 @@ def roofline_object(inst, k, precision, mean_d, launches, kname, counters):
         out.update(bound="mfma", achieved=m["issued"], peak=m["peak"], unit="TFLOP/s", frac=m["issued_frac"])
     elif "rocprof" in out:
         out["rocprof"]["frac"] = out["rocprof"]["hbm_frac"]
-    if cache_resident and out["bound"] == "hbm":
+    if cache_resident and out["bound"] == "hbm" and "note" not in out:
         out["note"] = "the state stays in the last-level cache: HBM is not the limiter, VALU counters not taken"
     return out
 

@@ -143,8 +143,12 @@ typedef struct mf_desc {
                              * tiles of 16 x 16 (B included) takes up to 4096 steps per
                              * launch in one resident workgroup per tile, the halo
                              * exchanged through the workspace after every step, when
-                             * the device keeps all those workgroups resident at once
-                             * (cooperative launch) */
+                             * the device can hold all those workgroups at once.  Its
+                             * tiles wait for each other: kernels on other streams
+                             * that occupy compute units for more than 20 ms during
+                             * such a launch make its waits give up (reported by
+                             * mf_check); set steps_per_launch > 0 where that can
+                             * happen */
   int32_t rule;            /* mf_rule (MF_RULE_FIXED = 0: the fixed-step proximal update) */
   float rule_gamma1;       /* MOMENTUM / ADAM: decay of the momentum average, in [0, 1) */
   float rule_gamma2;       /* ADAM: decay of the second moment, in [0, 1) */

@@ -34,8 +34,13 @@
 // matches.  Every wait is bounded (20 ms of the constant 100 MHz clock):
 // a wavefront that gives up sets bit 2 of the handle's flags and stops
 // waiting for the rest of the launch, so every workgroup finishes.  The
-// launch is cooperative: the runtime refuses it unless all tiles are
-// resident at once.
+// host launches it only when the occupancy query says every tile's
+// workgroup fits on the device at once (at 256 tiles: one per compute
+// unit).  Workgroups of kernels running beside it on other streams can
+// still hold compute units for a while; a tile that starts late only delays
+// its neighbours, unless it starts more than 20 ms late: then the waits give
+// up and the flag reports it.  (A cooperative launch, which would have the
+// runtime guarantee residency, measured 20 us slower per launch.)
 //
 // Arithmetic per node is that of the fused kernel, so with the same launch
 // boundaries the iterates match the fused kernel's bitwise (neighbours' q
@@ -365,9 +370,7 @@ int resident_per_cu() {
       n = 0;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
-    int coop = 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) coop = 0;
-    cached[dev] = coop ? n * cus : 0;
+    cached[dev] = n * cus;
     if (cached[dev] == 0) cached[dev] = -1;
   }
   return cached[dev] > 0 ? cached[dev] : 0;
@@ -380,11 +383,9 @@ hipError_t go(const StepArgs& a, const ExchangeArgs& x, hipStream_t s, bool quer
     return hipSuccess;
   }
   const int tiles = ((a.W + kT - 1) / kT) * ((a.H + kT - 1) / kT) * a.B;
-  StepArgs aa = a;
-  ExchangeArgs xx = x;
-  float om = (float)(1.0 - (double)a.alpha);
-  void* args[] = {&aa, &xx, &om};
-  return hipLaunchCooperativeKernel((const void*)persist_kernel<LG, LC, CONN, PREC>, dim3(tiles), dim3(kNT), args, 0, s);
+  const float om = (float)(1.0 - (double)a.alpha);
+  hipLaunchKernelGGL((persist_kernel<LG, LC, CONN, PREC>), dim3(tiles), dim3(kNT), 0, s, a, x, om);
+  return hipGetLastError();
 }
 
 template <int PREC>
@@ -425,7 +426,7 @@ int grid_persist_capacity(int L, int conn, int precision) {
   a.L = L;
   persist::ExchangeArgs x{};
   int cap = 0;
-  persist::dispatch(a, conn, precision, x, nullptr, true, &cap);
+  if (persist::dispatch(a, conn, precision, x, nullptr, true, &cap) != hipSuccess) return 0;
   return cap;
 }
 

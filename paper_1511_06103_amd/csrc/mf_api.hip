@@ -603,8 +603,8 @@ void* scratch_address(hipError_t* err) {
   return g_scratch_ptr[dev];
 }
 
-// The persistent kernel when the device keeps every tile's workgroup
-// resident at once (cooperative launch): no halo recomputation and one
+// The persistent kernel when the device can keep every tile's workgroup
+// resident at once (the occupancy query): no halo recomputation and one
 // launch per kPersistMaxSteps steps.
 bool choose_persist(const mf_desc& d) {
   if (!persist_possible(d)) return false;

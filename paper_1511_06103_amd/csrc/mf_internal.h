@@ -253,8 +253,7 @@ int grid_blocks_per_item(int H, int W);
 // Every step of a launch in one resident workgroup per 16 x 16 tile, the
 // halo exchanged through tagged words (grid_persist.hip): general Theta,
 // 8 < L <= kSmallLabels, at most kPersistMaxTiles tiles and no more than the
-// device keeps resident (grid_persist_capacity; 0 without cooperative
-// launch).  Steps per launch at most kPersistMaxSteps.  Bit 2 of flags: a
+// device keeps resident (grid_persist_capacity, from the occupancy query).  Steps per launch at most kPersistMaxSteps.  Bit 2 of flags: a
 // halo wait gave up.
 constexpr int kPersistMaxTiles = 256;
 constexpr int kPersistMaxSteps = 4096;

@@ -80,6 +80,21 @@ def test_roofline_bound_follows_the_counters():
     assert bench.roofline_object(g, 4, "f32", t, 10, "k", c)["bound"] == "hbm"
 
 
+def test_persistent_kernel_reports_the_effective_fraction():
+    """The persistent grid kernel is bound by the halo exchange: the line keeps
+    the effective HBM fraction as frac and says why, counters or not."""
+    g = synth.grid_theta_random(1, 32, 32, 21, synth.GRID8)
+    algo = bench.algorithmic_bytes(g, 100)
+    t = 3e-4
+    c = {"hbm_bytes_per_launch": algo // 50, "sq_insts_valu_per_launch": 5.0e7, "rocprof_avg_us": 310.0}
+    r = bench.roofline_object(g, 100, "f32", t, 10, "mf::persist::persist_kernel", c)
+    assert r["bound"] == "hbm" and "exchange" in r["note"]
+    assert abs(r["frac"] - algo / t / 1e9 / bench.HBM_PEAK_GBS) < 1e-4
+    assert "valu" in r and abs(r["rocprof"]["frac"] - algo / 310e-6 / 1e9 / bench.HBM_PEAK_GBS) < 1e-4
+    assert bench.step_kernel_name(g, 100, bench.PERSIST_STEPS) == "mf::persist::persist_kernel"
+    assert bench.source_kind(g, bench.PERSIST_STEPS) == "persist" and bench.source_kind(g, 4) == "grid"
+
+
 def test_many_label_grids_report_the_matrix_cores():
     g = synth.grid_theta_random(1, 4, 100, 128, synth.GRID8)
     fl = bench.mfma_flops_per_launch(g, 1, "f32")
