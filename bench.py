@@ -431,7 +431,7 @@ def beyond_cache(torch, mf, synth, launches):
     inst = synth.workload_big()
     solver = make_solver(inst, torch, mf)
     solver.solve(0)
-    mean_d, k = time_step_launches(solver, torch, launches, warm=10)
+    mean_d, k = time_step_launches(solver, torch, launches, warm=100)
     kname = step_kernel_name(inst, k)
     counters = load_counters(inst.name, k, source_kind(inst))
     r = roofline_object(inst, k, "f32", mean_d, launches, kname, counters)
