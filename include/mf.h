@@ -227,7 +227,8 @@ mf_status mf_marginals(mf_handle *h, float *q_out);
  * MF_ENONFINITE if a non-finite unary (or initial state) was seen, MF_EINVAL
  * for malformed CSR arrays, MF_EDEVICE on a HIP error or when a halo wait of
  * the persistent grid kernel gave up (its workgroups were not all resident;
- * the iterates of that launch are invalid; every wait is bounded, so the
+ * the iterates of that launch are invalid; every wait is bounded, 20 ms or
+ * the microseconds of the environment variable MF_PERSIST_WAIT_US, so the
  * launch still ends).  The conditions
  * accumulate over the initialisations since the handle was created or
  * since the last mf_check that reported one; reporting clears them. */

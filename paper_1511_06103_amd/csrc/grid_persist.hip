@@ -31,9 +31,13 @@
 // producer cannot publish step t + 2 into a slot before every reader of
 // step t in that slot has read it.  Tags are per launch (a base the host
 // advances past every tag it has used), so no word of an earlier launch
-// matches.  Every wait is bounded (20 ms of the constant 100 MHz clock):
-// a wavefront that gives up sets bit 2 of the handle's flags and stops
-// waiting for the rest of the launch, so every workgroup finishes.  The
+// matches.  Every wait is bounded (20 ms of the constant 100 MHz clock;
+// the environment variable MF_PERSIST_WAIT_US sets another bound): a
+// wavefront that gives up sets bit 2 of the handle's flags and stops
+// waiting for the rest of the launch, so every workgroup finishes.
+// Persistent launches of one process on one device are serialised across
+// streams (an event recorded after each), so two never share the compute
+// units.  The
 // host launches it only when the occupancy query says every tile's
 // workgroup fits on the device at once (at 256 tiles: one per compute
 // unit).  Workgroups of kernels running beside it on other streams can
@@ -50,6 +54,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
+#include <mutex>
+
 #include "grid_temporal.h"
 #include "mf_internal.h"
 #include "msg_codec.h"
@@ -62,7 +69,7 @@ constexpr int kR = kT + 2;                // region side: the tile and one node 
 constexpr int kRA = kR * kR;              // region nodes
 constexpr int kRingW = 64;                // exchange words per label plane, slot and tile (60 ring nodes)
 constexpr int kNT = 1024;                 // 16 wavefronts, one 16-node task each
-constexpr long long kWaitTicks = 2000000; // 20 ms at 100 MHz
+constexpr long long kWaitUs = 20000;     // default bound of one halo wait (20 ms)
 
 struct ExchangeArgs {
   uint64_t* xch;       // [tiles][2][L][kRingW] tagged words
@@ -71,6 +78,7 @@ struct ExchangeArgs {
   int* flags;          // bit 0: a non-finite input (with init >= 0); bit 2: a halo wait gave up
   int init;            // mf_init_mode applied to the state first, or -1 (the state is initialised)
   float* q_out;        // [B][L][N] q = exp(log q) of the last step, or nullptr
+  long long wait_ticks;  // bound of one halo wait, ticks of the 100 MHz constant clock
 };
 
 // k quarter turns clockwise inside the tile: (y, x) -> (x, 15 - y); also
@@ -273,7 +281,7 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
           }
         }
         if (!__any(pend != 0u)) break;
-        if (aborted || wall_clock64() - t0 > kWaitTicks) {
+        if (aborted || wall_clock64() - t0 > x.wait_ticks) {
           if (!aborted && lane == 0) atomicOr(x.flags, 4);
           aborted = true;
           break;
@@ -439,8 +447,40 @@ hipError_t launch_grid_persist(const StepArgs& a, int conn, int precision, uint6
   x.flags = flags;
   x.init = init;
   x.q_out = q_out;
+  // MF_PERSIST_WAIT_US overrides the bound of one halo wait (diagnostics:
+  // 0 makes every wait that finds a tag not yet written give up)
+  long long us = persist::kWaitUs;
+  if (const char* v = std::getenv("MF_PERSIST_WAIT_US")) {
+    char* end = nullptr;
+    const long long w = std::strtoll(v, &end, 10);
+    if (end != v && w >= 0) us = w;
+  }
+  x.wait_ticks = us * 100;
+  // Persistent launches of this process on one device run one after
+  // another, whatever their streams: two of them sharing the compute units
+  // would each wait for tiles the other keeps from starting.
+  static std::mutex mu;
+  static hipEvent_t last_ev[64] = {};
+  static hipStream_t last_stream[64] = {};
+  static bool have[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  // (A stream under graph capture takes no part: the graph's own order applies.)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return e;
   int cap = 0;
-  return persist::dispatch(a, conn, precision, x, s, false, &cap);
+  if (cs != hipStreamCaptureStatusNone) return persist::dispatch(a, conn, precision, x, s, false, &cap);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!last_ev[dev]) e = hipEventCreateWithFlags(&last_ev[dev], hipEventDisableTiming);
+  if (e == hipSuccess && have[dev] && last_stream[dev] != s) e = hipStreamWaitEvent(s, last_ev[dev], 0);
+  if (e == hipSuccess) e = persist::dispatch(a, conn, precision, x, s, false, &cap);
+  if (e == hipSuccess) e = hipEventRecord(last_ev[dev], s);
+  if (e == hipSuccess) {
+    have[dev] = true;
+    last_stream[dev] = s;
+  }
+  return e;
 }
 
 }  // namespace mf

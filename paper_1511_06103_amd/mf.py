@@ -267,6 +267,13 @@ class MeanField:
         d.workspace = _ptr(self.workspace)
         d.workspace_bytes = ws
         self.desc = d
+        caller = torch.cuda.current_stream(dev)
+        if self.stream != caller:
+            # the inputs were produced on the caller's stream; the buffers this
+            # object owns are used on its own stream from now on
+            self.stream.wait_stream(caller)
+            for t in (self.workspace, self.state_buf):
+                t.record_stream(self.stream)
         h = ctypes.c_void_p()
         _check(L_.mf_init(ctypes.byref(d), ctypes.byref(h)))
         self._handle = h

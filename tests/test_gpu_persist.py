@@ -184,3 +184,40 @@ def test_non_finite_unary_reported_by_the_one_launch_solve():
     with pytest.raises(mf.MFError) as e:
         s.check()
     assert e.value.status == mf.MF_ENONFINITE
+
+
+def test_wait_bound_gives_up_into_the_flags(c2, monkeypatch):
+    """With the halo-wait bound set to zero (MF_PERSIST_WAIT_US=0) every wait
+    that finds a tag not yet written gives up at once: the launch still ends,
+    and mf_check reports it; with the default bound the next solve is clean."""
+    from paper_1511_06103_amd import mf
+    s = cases.gpu_solver(c2)
+    monkeypatch.setenv("MF_PERSIST_WAIT_US", "0")
+    s.solve(20)
+    with pytest.raises(mf.MFError) as e:
+        s.check()
+    assert e.value.status == mf.MF_EDEVICE and "halo" in str(e.value)
+    monkeypatch.delenv("MF_PERSIST_WAIT_US")
+    s.solve(20)
+    assert s.check() is None
+    ref = cases.gpu_solver(c2)
+    ref.solve(20)
+    assert np.array_equal(state(s), state(ref))
+
+
+def test_launches_on_two_streams(c2):
+    """Persistent launches of two handles on two streams run one after the
+    other (never sharing the compute units): each matches its solo result."""
+    other = synth.grid_theta_random(31, 256, 256, 21, synth.GRID8, alpha=0.4, iters=30)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = cases.gpu_solver(c2, stream=s1)
+    b = cases.gpu_solver(other, stream=s2)
+    for n in (3, 2, 4, 3):
+        a.step(n)
+        b.step(n)
+    ra, rb = cases.gpu_solver(c2), cases.gpu_solver(other)
+    for n in (3, 2, 4, 3):
+        ra.step(n)
+        rb.step(n)
+    assert a.check() is None and b.check() is None
+    assert np.array_equal(state(a), state(ra)) and np.array_equal(state(b), state(rb))
