@@ -164,10 +164,7 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
   for (int j = 0; j < LG; ++j) valid[j] = (LC > 0 && 4 * j + 3 < LC) || g + 4 * j < L;
   uint64_t* __restrict__ my_x = x.xch + (size_t)tile * 2 * L * kRingW + (unsigned)(15 * wave + col);
 
-  // Both q buffers start at zero: off-grid halo cells, nodes past the
-  // grid's edge and padding label slots stay q = 0.
-  for (int f = tid; f < 2 * LP * RN; f += kNT) (&qs[0][0])[f] = M::enc(0.f);
-
+  // The node's log q and unaries (loads first: the LDS clear runs under them)
   float ell[LG], uu[LG];
 #pragma unroll
   for (int j = 0; j < LG; ++j) {
@@ -175,11 +172,27 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
     ell[j] = temporal::load_at(lin, off);
     uu[j] = temporal::load_at(ug, off);
   }
+  // with the initialisation from the unaries: this lane's group of LG
+  // consecutive labels g LG .. g LG + LG - 1
+  float ug4[LG];
+  if (x.init == MF_INIT_UNARY) {
+#pragma unroll
+    for (int j = 0; j < LG; ++j) {
+      const int l = g * LG + j;
+      ug4[j] = temporal::load_at(ug, ((unsigned)(l < L ? l : 0) * N + n) * 4u);
+    }
+  }
+
+  // Both q buffers start at zero: off-grid halo cells, nodes past the
+  // grid's edge and padding label slots stay q = 0.
+  for (int f = tid; f < 2 * LP * RN; f += kNT) (&qs[0][0])[f] = M::enc(0.f);
+
   if (x.init >= 0) {
     // log q^0 as the initialisation kernel forms it (Eq. 6 reading
-    // q^0 = softmax(-u), or uniform, or the given state): its four label
-    // groups of LG consecutive labels, each summed in order, combined as
-    // (s0 + s2) + (s1 + s3); every lane of a node forms the whole sum
+    // q^0 = softmax(-u), or uniform, or the given state): four label groups
+    // of LG consecutive labels, one per lane of the node, each with its own
+    // max and its own sum in label order; the maxima combined, the sums as
+    // (s0 + s2) + (s1 + s3), the same bits in every lane of the node
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < LG; ++j) {
@@ -187,20 +200,19 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
       if (valid[j] && x.init == MF_INIT_STATE) bad |= !isfinite(ell[j]);
     }
     if (x.init == MF_INIT_UNARY) {
-      const unsigned nb = n * 4u;
       float mx = -INFINITY;
-      for (int l = 0; l < L; ++l) mx = fmaxf(mx, -temporal::load_at(ug, (unsigned)l * N * 4u + nb));
-      float sg[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        sg[k] = 0.f;
+      for (int j = 0; j < LG; ++j) mx = fmaxf(mx, g * LG + j < L ? -ug4[j] : -INFINITY);
+      mx = temporal::rows_max(mx);
+      float sg = 0.f;
 #pragma unroll
-        for (int j = 0; j < LG; ++j) {
-          const int l = k * LG + j;
-          sg[k] += l < L ? expf(-temporal::load_at(ug, (unsigned)(l < L ? l : 0) * N * 4u + nb) - mx) : 0.f;
-        }
-      }
-      const float lse = mx + logf((sg[0] + sg[2]) + (sg[1] + sg[3]));
+      for (int j = 0; j < LG; ++j) sg += g * LG + j < L ? expf(-ug4[j] - mx) : 0.f;
+      // rows g and g ^ 2 first (the two half-waves), then the two pairs
+      const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(sg), __float_as_uint(sg), false, false);
+      sg = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+      const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(sg), __float_as_uint(sg), false, false);
+      sg = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+      const float lse = mx + logf(sg);
 #pragma unroll
       for (int j = 0; j < LG; ++j) ell[j] = -uu[j] - lse;
     } else if (x.init == MF_INIT_UNIFORM) {
