@@ -53,6 +53,10 @@ extern "C" {
    graphs, the other step rules, mf_step_many's shared launches, the adjoint
    and the power method take up to 32 (MF_EUNSUPPORTED above). */
 #define MF_MAX_LABELS 128
+
+/* Steps per launch of the persistent grid kernel (see mf_desc.steps_per_launch),
+ * as mf_steps_per_launch reports it for a handle that runs that kernel. */
+#define MF_PERSIST_STEPS_PER_LAUNCH 4096
 /* n_labels * n_nodes of one problem must stay below this (2^30): the kernels
    address one problem's [L][N] planes with 32-bit byte offsets.  Larger
    problems are rejected with MF_EUNSUPPORTED. */

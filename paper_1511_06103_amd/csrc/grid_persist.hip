@@ -162,7 +162,10 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
   bool valid[LG];
 #pragma unroll
   for (int j = 0; j < LG; ++j) valid[j] = (LC > 0 && 4 * j + 3 < LC) || g + 4 * j < L;
-  uint64_t* __restrict__ my_x = x.xch + (size_t)tile * 2 * L * kRingW + (unsigned)(15 * wave + col);
+  // this tile's exchange area (both slots); a ring lane's node sits at
+  // position 15 wave + col of each label plane
+  uint64_t* __restrict__ my_x = x.xch + (size_t)tile * 2 * L * kRingW;
+  const unsigned rpos = ring ? (unsigned)(15 * wave + col) : 0u;
 
   // The node's log q and unaries (loads first: the LDS clear runs under them)
   float ell[LG], uu[LG];
@@ -231,7 +234,8 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
         qs[0][cb + 4 * j * RN] = e;
         if (ring) {
           const uint64_t w = ((uint64_t)x.tag0 << 32) | __float_as_uint(M::dec(e));
-          __hip_atomic_store(my_x + (unsigned)((g + 4 * j) * kRingW), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(my_x + (unsigned)((g + 4 * j) * kRingW) + rpos, w, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
         qn[cb + 4 * j * RN] = qv;
         if (ring) {
           const uint64_t w = ((uint64_t)tag << 32) | __float_as_uint(M::dec(qv));
-          __hip_atomic_store(my_x + nslot + (unsigned)((g + 4 * j) * kRingW), w, __ATOMIC_RELAXED,
+          __hip_atomic_store(my_x + nslot + (unsigned)((g + 4 * j) * kRingW) + rpos, w, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
         }
       }

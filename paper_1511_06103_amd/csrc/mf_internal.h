@@ -256,7 +256,7 @@ int grid_blocks_per_item(int H, int W);
 // device keeps resident (grid_persist_capacity, from the occupancy query).  Steps per launch at most kPersistMaxSteps.  Bit 2 of flags: a
 // halo wait gave up.
 constexpr int kPersistMaxTiles = 256;
-constexpr int kPersistMaxSteps = 4096;
+constexpr int kPersistMaxSteps = MF_PERSIST_STEPS_PER_LAUNCH;
 bool grid_persist_eligible(int L, int compat);
 size_t grid_persist_exchange_bytes(int B, int H, int W, int L);
 int grid_persist_capacity(int L, int conn, int precision);

@@ -21,6 +21,7 @@ MF_ABI_VERSION = 3
 MF_MAX_LABELS = 128   # grids with the fixed-step rule; 32 elsewhere
 MF_SMALL_LABELS = 32
 MF_STATIC_SCRATCH_BYTES = 64 << 20   # scratch array of mf_solve_static, per GPU
+MF_PERSIST_STEPS_PER_LAUNCH = 4096   # steps per launch reported for the persistent grid kernel
 MF_MAX_LABEL_NODES = 1 << 30   # n_labels * n_nodes of one problem must stay below this
 
 MF_OK, MF_EINVAL, MF_ENONFINITE, MF_EDEVICE, MF_EUNSUPPORTED, MF_ENOWORKSPACE = 0, -1, -2, -3, -4, -5

@@ -80,6 +80,15 @@ def test_roofline_bound_follows_the_counters():
     assert bench.roofline_object(g, 4, "f32", t, 10, "k", c)["bound"] == "hbm"
 
 
+def test_persistent_step_count_matches_the_header():
+    import os
+    import re
+    from paper_1511_06103_amd import mf
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mf.h")).read()
+    v = int(re.search(r"#define MF_PERSIST_STEPS_PER_LAUNCH (\d+)", text).group(1))
+    assert v == mf.MF_PERSIST_STEPS_PER_LAUNCH == bench.PERSIST_STEPS
+
+
 def test_persistent_kernel_reports_the_effective_fraction():
     """The persistent grid kernel is bound by the halo exchange: the line keeps
     the effective HBM fraction as frac and says why, counters or not."""

@@ -22,7 +22,7 @@ from paper_1511_06103_amd import synth  # noqa: E402
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-PERSIST_STEPS = 4096   # steps per launch the library reports for the persistent kernel
+from paper_1511_06103_amd.mf import MF_PERSIST_STEPS_PER_LAUNCH as PERSIST_STEPS  # noqa: E402
 
 
 @pytest.fixture(scope="module", autouse=True)
