@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
           aborted = true;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
       }
       // this wavefront's LDS writes above come before its reads below
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
