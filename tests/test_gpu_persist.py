@@ -221,3 +221,35 @@ def test_launches_on_two_streams(c2):
         rb.step(n)
     assert a.check() is None and b.check() is None
     assert np.array_equal(state(a), state(ra)) and np.array_equal(state(b), state(rb))
+
+
+@pytest.mark.parametrize("L", [9, 12, 16, 17, 21, 24, 25, 32])
+@pytest.mark.parametrize("conn", [synth.GRID4, synth.GRID8])
+def test_every_label_count(L, conn):
+    """Each label-slot instantiation (4, 6 or 8 slots per lane, the L = 21
+    one compiled in) on a 40 x 50 grid: bitwise equal to the fused kernel
+    over one launch of two steps, then 8 more steps against the oracle."""
+    inst = synth.grid_theta_random(500 + L + conn, 40, 50, L, conn, alpha=0.5, iters=10)
+    s = cases.gpu_solver(inst)
+    assert s.steps_per_launch == PERSIST_STEPS
+    f, k = fused_like(inst)
+    s.step(2)
+    f.step(2)
+    assert np.array_equal(state(s), state(f))
+    s.step(8)
+    assert s.check() is None
+    ref = O.solve(cases.oracle_model(inst), 0.5, 10)[-1]
+    assert cases.max_dq(state(s)[0].astype(np.float64), ref) <= 1e-5
+
+
+def test_batch_of_small_grids():
+    """Four 64 x 64 problems (64 tiles in one launch) against the oracle."""
+    inst = synth.grid_theta_random(77, 64, 64, 21, synth.GRID8, batch=4, alpha=0.5, iters=10)
+    s = cases.gpu_solver(inst)
+    assert s.steps_per_launch == PERSIST_STEPS
+    s.solve(10)
+    assert s.check() is None
+    g = state(s)
+    for b in range(4):
+        ref = O.solve(cases.oracle_model(inst, b), 0.5, 10)[-1]
+        assert cases.max_dq(g[b].astype(np.float64), ref) <= 1e-5, b
