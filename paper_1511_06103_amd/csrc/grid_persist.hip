@@ -104,13 +104,14 @@ __device__ inline int ring_index(int y, int x) {
 template <int LG, int LC, int CONN, int PREC>
 __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x, float one_minus_alpha) {
   using M = MsgT<PREC>;
-  using T = typename M::T;
   constexpr int LP = 4 * LG;
   constexpr int NOB = (LG + 3) / 4;
   constexpr int RN = temporal::mfma_plane_stride(kRA);
   constexpr int NH = CONN == 8 ? 19 : 16;           // halo cells a ring wavefront reads
   constexpr int NF = (NH * LP + 63) / 64;           // (cell, label) pairs per lane
-  __shared__ T qs[2][LP * RN];
+  // q in LDS as FP32 values of the message type (16-bit messages decoded on
+  // write): the stencil reads full dwords whatever the message precision
+  __shared__ float qs[2][LP * RN];
 
   const int L = LC > 0 ? LC : a.L;
   const unsigned N = (unsigned)a.N;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
 
   // Both q buffers start at zero: off-grid halo cells, nodes past the
   // grid's edge and padding label slots stay q = 0.
-  for (int f = tid; f < 2 * LP * RN; f += kNT) (&qs[0][0])[f] = M::enc(0.f);
+  for (int f = tid; f < 2 * LP * RN; f += kNT) (&qs[0][0])[f] = 0.f;
 
   if (x.init >= 0) {
     // log q^0 as the initialisation kernel forms it (Eq. 6 reading
@@ -230,10 +231,10 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
 #pragma unroll
     for (int j = 0; j < LG; ++j) {
       if (valid[j]) {
-        const T e = M::enc(__expf(ell[j]));
+        const float e = M::dec(M::enc(__expf(ell[j])));
         qs[0][cb + 4 * j * RN] = e;
         if (ring) {
-          const uint64_t w = ((uint64_t)x.tag0 << 32) | __float_as_uint(M::dec(e));
+          const uint64_t w = ((uint64_t)x.tag0 << 32) | __float_as_uint(e);
           __hip_atomic_store(my_x + (unsigned)((g + 4 * j) * kRingW) + rpos, w, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -275,8 +276,8 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
   bool aborted = false;
   for (int s = 0; s < x.ks; ++s) {
     const int cur = s & 1;
-    T* __restrict__ qc = qs[cur];
-    T* __restrict__ qn = qs[cur ^ 1];
+    float* __restrict__ qc = qs[cur];
+    float* __restrict__ qn = qs[cur ^ 1];
     if (wave < 4) {
       // the halo of step s: words of slot s % 2 tagged tag0 + s
       const unsigned expect = x.tag0 + (unsigned)s;
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
 #pragma unroll
         for (int it = 0; it < NF; ++it) {
           if (((pend >> it) & 1u) && (unsigned)(w[it] >> 32) == expect) {
-            qc[loff[it]] = M::enc(__uint_as_float((unsigned)w[it]));
+            qc[loff[it]] = __uint_as_float((unsigned)w[it]);
             pend &= ~(1u << it);
           }
         }
@@ -310,14 +311,14 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
     }
 
     // LDS byte address of plane g at region offset - kR - 1 of this node
-    const unsigned qb = temporal::lds_addr(qc) + (unsigned)(cb - kR - 1) * (unsigned)sizeof(T);
+    const unsigned qb = temporal::lds_addr(qc) + (unsigned)(cb - kR - 1) * 4u;
     float S[LG];
 #pragma unroll
     for (int j = 0; j < LG; ++j) {
-      const T* qp = temporal::lds_ptr<T>(temporal::opaque(qb + (unsigned)(4 * j * RN) * (unsigned)sizeof(T)));
-      const float n0 = M::dec(qp[1]), w0 = M::dec(qp[kR]), e0 = M::dec(qp[kR + 2]), s0 = M::dec(qp[2 * kR + 1]);
+      const float* qp = temporal::lds_ptr<float>(temporal::opaque(qb + (unsigned)(4 * j * RN) * 4u));
+      const float n0 = qp[1], w0 = qp[kR], e0 = qp[kR + 2], s0 = qp[2 * kR + 1];
       float tot = (n0 + w0) + (e0 + s0);
-      if (CONN == 8) tot += (M::dec(qp[0]) + M::dec(qp[2])) + (M::dec(qp[2 * kR]) + M::dec(qp[2 * kR + 2]));
+      if (CONN == 8) tot += (qp[0] + qp[2]) + (qp[2 * kR] + qp[2 * kR + 2]);
       S[j] = valid[j] ? tot : 0.f;
     }
 
@@ -356,10 +357,10 @@ __global__ __launch_bounds__(kNT) void persist_kernel(StepArgs a, ExchangeArgs x
     for (int j = 0; j < LG; ++j) {
       ell[j] = z[j] - lse;
       if (act && valid[j]) {
-        const T qv = M::enc(e[j] * inv);
+        const float qv = M::dec(M::enc(e[j] * inv));
         qn[cb + 4 * j * RN] = qv;
         if (ring) {
-          const uint64_t w = ((uint64_t)tag << 32) | __float_as_uint(M::dec(qv));
+          const uint64_t w = ((uint64_t)tag << 32) | __float_as_uint(qv);
           __hip_atomic_store(my_x + nslot + (unsigned)((g + 4 * j) * kRingW) + rpos, w, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
         }
