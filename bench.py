@@ -496,6 +496,10 @@ def main():
                     help="back-to-back launches timed on the 2048 x 2048 grid")
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16", "f16"],
                     help="neighbour-message precision (the state and the step stay FP32)")
+    ap.add_argument("--steps-per-launch", type=int, default=None,
+                    help="--mode kernel: steps per launch (default: the library's choice)")
+    ap.add_argument("--warm-launches", type=int, default=2,
+                    help="--mode kernel: untimed launches before the timed ones")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -527,14 +531,15 @@ def main():
         if args.precision != "f32":
             sys.exit("the adjoint runs with FP32 messages only")
         return bench_adjoint(args, inst, torch, mf)
-    solver = make_solver(inst, torch, mf, precision=args.precision)
+    extra = {} if args.mode != "kernel" or args.steps_per_launch is None else {"steps_per_launch": args.steps_per_launch}
+    solver = make_solver(inst, torch, mf, precision=args.precision, **extra)
     q = torch.empty_like(solver.unary)
 
     if args.mode == "kernel":
         # only the dominant kernel, back to back, timed with HIP events on its
         # stream (the figure to set beside a profiler's average of the same run)
         solver.solve(0)
-        mean_d, k = time_step_launches(solver, torch, args.launches, warm=2, iters=T)
+        mean_d, k = time_step_launches(solver, torch, args.launches, warm=args.warm_launches, iters=T)
         log(f"kernel mode: {args.launches} launches of {k} steps, {mean_d * 1e6:.2f} us mean per launch "
             f"(HIP events)")
         return

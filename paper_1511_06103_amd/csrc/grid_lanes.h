@@ -97,6 +97,25 @@ struct Smem {
   float theta[G::LP * G::LS];
 };
 
+// One problem's [L][N] planes as a raw buffer resource (range = their byte
+// extent, dword 3 = the 32-bit data format of CDNA raw buffers).  Loads and
+// stores through it take a 32-bit per-lane byte offset plus a wavefront-
+// uniform scalar one: no 64-bit address arithmetic per lane and access.
+// Byte offsets fit in 32 bits because L N < 2^30 is checked at creation.
+__device__ inline __amdgpu_buffer_rsrc_t planes_rsrc(const float* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)bytes, 0x00020000);
+}
+// aux bit 1: non-temporal (the nt bit of the access)
+constexpr int kBufNt = 2;
+template <int AUX>
+__device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+}
+template <int AUX>
+__device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, AUX);
+}
+
 // Normalise z over the valid slots and store z - lse(z) as log q'.
 template <int LG>
 __device__ inline void store_normalised(float* __restrict__ out, const bool (&valid)[LG], const float (&z)[LG],
@@ -253,17 +272,26 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
 
   // All global loads first: own labels, this thread's share of the halo, Theta.
   // Addresses are clamped into range and the value is selected afterwards, so
-  // no load is skipped by a branch.
+  // no load is skipped by a branch.  With one lane per node the label
+  // plane's offset is the same in every lane (the scalar offset).
+  const unsigned pbytes = (unsigned)L * N * 4u;
+  const __amdgpu_buffer_rsrc_t rl = planes_rsrc(lin, pbytes), ru = planes_rsrc(ug, pbytes);
+  constexpr int kUAux = STREAM ? kBufNt : 0;
   bool valid[LG];
   float ell[LG], uu[LG];
 #pragma unroll
   for (int j = 0; j < LG; ++j) {
     const int l = sub * LG + j;
     valid[j] = l < L;
-    const unsigned lc = (unsigned)(l < L ? l : L - 1);
-    ell[j] = lin[lc * N + n];
-    if constexpr (STREAM) uu[j] = __builtin_nontemporal_load(&ug[lc * N + n]);
-    else uu[j] = ug[lc * N + n];
+    if constexpr (LPN == 1) {
+      const unsigned so = (unsigned)(j < L ? j : L - 1) * N * 4u;
+      ell[j] = buf_load<0>(rl, n * 4u, so);
+      uu[j] = buf_load<kUAux>(ru, n * 4u, so);
+    } else {
+      const unsigned vo = ((unsigned)(l < L ? l : L - 1) * N + n) * 4u;
+      ell[j] = buf_load<0>(rl, vo, 0u);
+      uu[j] = buf_load<kUAux>(ru, vo, 0u);
+    }
   }
   float hv[HREG];
 #pragma unroll
@@ -275,7 +303,7 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
     const int gy = y0 + hy - 1, gx = x0 + hx - 1;
     const bool ok = f < LP * HALO && l < L && gy >= 0 && gy < H && gx >= 0 && gx < W;
     const unsigned off = ok ? (unsigned)l * N + (unsigned)(gy * W + gx) : 0u;
-    const float v = lin[off];
+    const float v = buf_load<0>(rl, off * 4u, 0u);
     hv[r] = ok ? v : -INFINITY;
   }
   float tv[TREG > 0 ? TREG : 1];
@@ -371,13 +399,13 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
   for (int j = 0; j < LG; ++j) se += __expf(z[j] - mx);   // exp(-inf) = 0 for empty slots
   se = group_sum<LPN>(se);
   const float lse = mx + __logf(se);
-  float* __restrict__ out = a.state_out + base;
+  const __amdgpu_buffer_rsrc_t ro = planes_rsrc(a.state_out + base, pbytes);
 #pragma unroll
   for (int j = 0; j < LG; ++j) {
     const int l = sub * LG + j;
     if (valid[j]) {
-      if constexpr (STREAM) __builtin_nontemporal_store(z[j] - lse, &out[(unsigned)l * N + n]);
-      else out[(unsigned)l * N + n] = z[j] - lse;
+      if constexpr (LPN == 1) buf_store<kUAux>(z[j] - lse, ro, n * 4u, (unsigned)j * N * 4u);
+      else buf_store<kUAux>(z[j] - lse, ro, ((unsigned)l * N + n) * 4u, 0u);
     }
   }
 }
@@ -437,7 +465,12 @@ __global__ __launch_bounds__(TX * TY * LPN) void step_many_kernel(ManyArgs m) {
 // per node, 64 x 4 / 32 x 4 / 16 x 4 / 16 x 8 tiles) all took 10-13 us per
 // step there, while on the 2048 x 2048 grid one lane per node streamed
 // fastest (277 us per step against 346-508 us).  The label-parallel split
-// pays off in the fused multi-step kernel (grid_temporal.h) instead.
+// pays off in the fused multi-step kernel (grid_temporal.h) instead.  Grids
+// whose arrays stream past the cache take 64 x 12 tiles: on 2048 x 2048,
+// L = 21 they ran at 208 us per step against 222 us for 64 x 4 (64 x 8:
+// 215, 32 x 8: 218, 128 x 4: 243, 64 x 16: 275; shapes whose wavefront
+// count is not a multiple of the four SIMDs, 64 x 5 and 64 x 10, 258 and
+// 320 us).
 inline int slots_for(int L) {
   return L == 2 ? 2 : L == 21 ? 21 : L <= 4 ? 4 : L <= 8 ? 8 : L <= 16 ? 16 : 32;
 }
@@ -486,9 +519,12 @@ struct ForPrec {
     }
     return hipGetLastError();
   }
+  // Streaming launches take tiles three times as tall (64 x 12: twelve
+  // wavefronts, two workgroups and six wavefronts per SIMD at L = 21 where
+  // 64 x 4 fits four and four)
   template <int LG, int LPN, int LC, int TX, int TY>
   static hipError_t one(const StepArgs& a, int conn, int compat, hipStream_t s) {
-    return streams_past_cache(a) ? one_s<LG, LPN, LC, TX, TY, true>(a, conn, compat, s)
+    return streams_past_cache(a) ? one_s<LG, LPN, LC, TX, 3 * TY, true>(a, conn, compat, s)
                                  : one_s<LG, LPN, LC, TX, TY, false>(a, conn, compat, s);
   }
   template <int LG, int LPN, int LC, int TX, int TY>
