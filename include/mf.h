@@ -59,7 +59,9 @@ extern "C" {
 #define MF_PERSIST_STEPS_PER_LAUNCH 4096
 /* n_labels * n_nodes of one problem must stay below this (2^30): the kernels
    address one problem's [L][N] planes with 32-bit byte offsets.  Larger
-   problems are rejected with MF_EUNSUPPORTED. */
+   problems are rejected with MF_EUNSUPPORTED.  General graphs (MF_CSR) also
+   need n_nodes * LQ * 4 < 2^32, LQ = n_labels rounded up to 4 (L <= 12) or
+   to 8: the node-major q rows they gather are addressed the same way. */
 #define MF_MAX_LABEL_NODES ((size_t)1 << 30)
 
 typedef enum {

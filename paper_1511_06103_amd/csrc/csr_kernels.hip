@@ -45,6 +45,18 @@ __global__ __launch_bounds__(kCsrThreads) void csr_check_kernel(const int* __res
   if (bad) atomicOr(flags, 2);
 }
 
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+
+// A raw buffer resource over bytes [0, bytes) of p (dword 3: the 32-bit
+// data format of CDNA raw buffers).
+__device__ inline __amdgpu_buffer_rsrc_t csr_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline float rd32(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0u, 0));
+}
+
 // Four consecutive labels of a node-major q row: one 16-byte load in FP32,
 // one 8-byte load of 16-bit values in the BF16 / FP16 message modes (the
 // operand rounding of the neighbour aggregation, as on grids).
@@ -66,6 +78,21 @@ struct Q4 {
     } else {
       v[0] = dec16(c.x & 0xFFFFu); v[1] = dec16(c.x >> 16);
       v[2] = dec16(c.y & 0xFFFFu); v[3] = dec16(c.y >> 16);
+    }
+  }
+  // four labels of a row through a buffer resource
+  __device__ static C load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    if constexpr (PREC == P_F32) {
+      return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0u, 0));
+    } else {
+      return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0u, 0));
+    }
+  }
+  __device__ static void store(const C& c, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    if constexpr (PREC == P_F32) {
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u32, c), r, off, 0u, 0);
+    } else {
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, c), r, off, 0u, 0);
     }
   }
   __device__ static C enc(float a, float b, float c, float d) {
@@ -131,43 +158,59 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
     __syncthreads();
   }
   if (i >= N) return;   // both lanes of a node leave together
+  // Buffer resources over this problem's arrays: every access below is a
+  // 32-bit byte offset (L N < 2^30, N LQ 4 < 2^32 and nnz < 2^31 are
+  // checked at creation), no 64-bit address arithmetic per lane.
   const size_t base = (size_t)b * L * N;
-  const float* __restrict__ li = a.state_in + base + i;
-  const float* __restrict__ ui = a.unary + base + i;
+  const unsigned pbytes = (unsigned)L * (unsigned)N * 4u;
+  const __amdgpu_buffer_rsrc_t rl = csr_rsrc(a.state_in + base, pbytes);
+  const __amdgpu_buffer_rsrc_t ru = csr_rsrc(a.unary + base, pbytes);
   const int l0 = h * LH;
 
+  // log q and u of the node's labels: loaded before the gather in FP32 (their
+  // latency hides under it), after it with 16-bit rows, where the registers
+  // freed during the gather keep more wavefronts resident (60 against 87).
   float ell[LH], uu[LH];
+  auto load_state = [&]() {
 #pragma unroll
-  for (int u = 0; u < LH; ++u) {
-    const int l = l0 + u;
-    const size_t at = (size_t)(l < L ? l : L - 1) * N;   // clamped: no branch
-    const float x = li[at], y = ui[at];
-    ell[u] = l < L ? x : 0.f;
-    uu[u] = l < L ? y : 0.f;
-  }
+    for (int u = 0; u < LH; ++u) {
+      const int l = l0 + u;
+      const unsigned at = ((unsigned)(l < L ? l : L - 1) * (unsigned)N + (unsigned)i) * 4u;   // clamped: no branch
+      const float x = rd32(rl, at), y = rd32(ru, at);
+      ell[u] = l < L ? x : 0.f;
+      uu[u] = l < L ? y : 0.f;
+    }
+  };
+  if constexpr (PREC == P_F32) load_state();
 
   float S[LH];
 #pragma unroll
   for (int u = 0; u < LH; ++u) S[u] = 0.f;
-  const C* __restrict__ qb = reinterpret_cast<const C*>(a.q_in) + (size_t)b * N * (LQ / 4) + h * (LH / 4);
+  constexpr unsigned kRow = (LQ / 4) * sizeof(C);         // bytes of one node-major q row
+  const __amdgpu_buffer_rsrc_t rq =
+      csr_rsrc(reinterpret_cast<const C*>(a.q_in) + (size_t)b * N * (LQ / 4), (unsigned)N * kRow);
+  const unsigned hoff = (unsigned)(h * (LH / 4)) * (unsigned)sizeof(C);
+  const int nnz = (int)a.nnz;
+  const __amdgpu_buffer_rsrc_t rc = csr_rsrc(a.col, (unsigned)nnz * 4u);
+  const __amdgpu_buffer_rsrc_t rw = csr_rsrc(a.w, a.w ? (unsigned)nnz * 4u : 0u);
   // Clamp the row to [0, nnz) and skip out-of-range columns: a malformed CSR
   // (reported through the flags by csr_check_kernel) never reads out of bounds.
-  long long e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+  int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
   e0 = e0 < 0 ? 0 : e0;
-  e1 = e1 > a.nnz ? a.nnz : e1;
+  e1 = e1 > nnz ? nnz : e1;
   // EB edges per trip: their column indices, then their q rows, are loaded
   // together.  Edges past the row end (and out-of-range columns) get weight
   // 0 and a valid address; the products are added in edge order.
   constexpr int EB = 4;
-  for (long long e = e0; e < e1; e += EB) {
+  for (int e = e0; e < e1; e += EB) {
     int j[EB];
     float w[EB];
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const bool on = e + u < e1;
-      const long long ec = on ? e + u : e0;
-      const int jj = a.col[ec];
-      const float ww = a.w ? a.w[ec] : 1.f;
+      const unsigned ec = (unsigned)(on ? e + u : e0) * 4u;
+      const int jj = (int)__builtin_amdgcn_raw_buffer_load_b32(rc, ec, 0u, 0);
+      const float ww = a.w ? rd32(rw, ec) : 1.f;
       const bool ok = on && jj >= 0 && jj < N;
       j[u] = ok ? jj : 0;
       w[u] = ok ? ww : 0.f;
@@ -175,9 +218,9 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
     C v[EB][LH / 4];
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
-      const C* qj = qb + (size_t)j[u] * (LQ / 4);
+      const unsigned qo = (unsigned)j[u] * kRow + hoff;
 #pragma unroll
-      for (int k = 0; k < LH / 4; ++k) v[u][k] = qj[k];
+      for (int k = 0; k < LH / 4; ++k) v[u][k] = Q::load(rq, qo + (unsigned)(k * sizeof(C)));
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
@@ -190,6 +233,8 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
       }
     }
   }
+
+  if constexpr (PREC != P_F32) load_state();
 
   // S of all LQ labels in label order: own half and the partner's
   float Sa[LQ];
@@ -239,14 +284,18 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
   }
   const float lse = mx + __logf(se);
   const float inv = 1.0f / se;
-  float* __restrict__ out = a.state_out + base + i;
+  const __amdgpu_buffer_rsrc_t ro = csr_rsrc(a.state_out + base, pbytes);
 #pragma unroll
   for (int u = 0; u < LH; ++u)
-    if (l0 + u < L) out[(size_t)(l0 + u) * N] = z[u] - lse;
-  C* qo = reinterpret_cast<C*>(a.q_out) + ((size_t)b * N + i) * (LQ / 4) + h * (LH / 4);
+    if (l0 + u < L)
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(z[u] - lse), ro,
+                                            ((unsigned)(l0 + u) * (unsigned)N + (unsigned)i) * 4u, 0u, 0);
+  const __amdgpu_buffer_rsrc_t rqo =
+      csr_rsrc(reinterpret_cast<const C*>(a.q_out) + (size_t)b * N * (LQ / 4), (unsigned)N * kRow);
 #pragma unroll
   for (int k = 0; k < LH / 4; ++k)
-    qo[k] = Q::enc(e[4 * k] * inv, e[4 * k + 1] * inv, e[4 * k + 2] * inv, e[4 * k + 3] * inv);
+    Q::store(Q::enc(e[4 * k] * inv, e[4 * k + 1] * inv, e[4 * k + 2] * inv, e[4 * k + 3] * inv), rqo,
+             (unsigned)i * kRow + hoff + (unsigned)(k * sizeof(C)));
 }
 
 __device__ inline double wave_sum_d(double v) {

@@ -165,6 +165,11 @@ mf_status check_desc(const mf_desc* d, std::string* msg) {
     *msg = "n_labels * n_nodes must be below MF_MAX_LABEL_NODES per problem";
     return MF_EUNSUPPORTED;
   }
+  if (d->graph == MF_CSR &&
+      (size_t)d->n_nodes * (size_t)mf::csr_label_stride(d->n_labels) * sizeof(float) >= ((size_t)1 << 32)) {
+    *msg = "general graphs: n_nodes * (n_labels rounded up to 4 or 8) * 4 bytes must be below 2^32";
+    return MF_EUNSUPPORTED;
+  }
   if (d->graph == MF_CSR) {
     if (!d->csr_row_ptr) return bad("csr_row_ptr is NULL");
     if (d->csr_nnz < 0 || d->csr_nnz > INT32_MAX) return bad("csr_nnz out of range");

@@ -167,6 +167,16 @@ def csr_desc(**kw):
     return good_desc(**base)
 
 
+def test_csr_gathered_rows_limit():
+    """General graphs: the node-major q rows (N x LQ floats, LQ = 24 for
+    L = 17) must stay below 4 GiB, besides L * N < 2^30."""
+    far = dict(state=FAKE + (1 << 40), workspace=FAKE + (1 << 42), workspace_bytes=1 << 44)
+    n_ok, n_big = 40 << 20, 50 << 20          # 40 Mi x 96 B < 4 GiB <= 50 Mi x 96 B; L N < 2^30 for both
+    assert validate(csr_desc(n_labels=17, n_nodes=n_ok, **far)) == mf.MF_OK
+    assert validate(csr_desc(n_labels=17, n_nodes=n_big, **far)) == mf.MF_EUNSUPPORTED
+    assert "2^32" in mf.last_error()
+
+
 def test_csr_descriptor_validation():
     assert validate(csr_desc()) == mf.MF_OK
     assert validate(csr_desc(csr_w=FAKE + (1 << 38))) == mf.MF_OK
