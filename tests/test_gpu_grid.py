@@ -442,6 +442,48 @@ def test_largest_problem_init_and_step_sampled():
     assert worst0 <= 1e-6 and worst1 <= 1e-6, (worst0, worst1)
 
 
+@pytest.mark.parametrize("conn,precision,tol", [(8, "f32", 1e-6), (4, "f32", 1e-6), (8, "bf16", 2e-3)])
+def test_streaming_tiles_ragged_both_ways_sampled(conn, precision, tol):
+    """A grid whose arrays stream past the cache (1499 x 3001, L = 21: 378 MB
+    per array) runs the single-step kernel on 64 x 12 tiles; neither side is
+    a multiple of the tile, so the last tile row and column are partial.  One
+    step from the initialisation against the oracle at sampled nodes, the
+    edges and corners of both partial tiles included (the message-precision
+    bound with BF16 messages)."""
+    from paper_1511_06103_amd import mf
+    H, W, L = 1499, 3001, 21
+    N = H * W
+    assert 12 * L * N > 256 << 20 and H % 12 and W % 64
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(30 + conn)
+    u = -torch.log_softmax(2.0 * torch.randn((1, L, N), generator=gen, device=dev), dim=1)
+    th = np.triu(np.random.default_rng(31).uniform(0.0, 2.0, (L, L)), 1)
+    th = (th + th.T).astype(np.float32)
+    s = mf.MeanField(u, "grid8" if conn == 8 else "grid4", height=H, width=W,
+                     theta=torch.from_numpy(th).to(dev), alpha=0.5, precision=precision)
+    assert s.steps_per_launch == 1
+    rng = np.random.default_rng(32)
+    ey, ex = (H // 12) * 12, (W // 64) * 64          # first row / column of the partial tiles
+    ys = np.concatenate([rng.integers(0, H, 250), [0, 0, H - 1, H - 1, ey, ey - 1, ey, H - 1, ey]])
+    xs = np.concatenate([rng.integers(0, W, 250), [0, W - 1, 0, W - 1, ex, ex - 1, W - 1, ex, ex - 1]])
+    idx = torch.from_numpy((ys * W + xs).astype(np.int64)).to(dev)
+    s.step(1)
+    got = s.current_state()[0][:, idx].cpu().numpy().astype(np.float64)
+    s.check()
+    worst = 0.0
+    for k, (y, x) in enumerate(zip(ys, xs)):
+        y0, y1, x0, x1 = max(0, y - 1), min(H, y + 2), max(0, x - 1), min(W, x + 2)
+        nodes = (np.arange(y0, y1)[:, None] * W + np.arange(x0, x1)[None, :]).ravel()
+        uu = u[0][:, torch.from_numpy(nodes).to(dev)].cpu().numpy().astype(np.float64)
+        ell0 = O.init_state(uu).astype(np.float32).astype(np.float64)
+        sub = O.grid_model(uu, y1 - y0, x1 - x0, conn, theta=th.astype(np.float64))
+        ref = O.prox_step(ell0, sub, 0.5)
+        c = (y - y0) * (x1 - x0) + (x - x0)
+        worst = max(worst, cases.max_dq(got[:, k], ref[:, c]))
+    s.close()
+    assert worst <= tol, (conn, precision, worst)
+
+
 def test_big_grid_one_step_sampled():
     inst = synth.workload_big()
     H, W, L = inst.height, inst.width, inst.n_labels
