@@ -93,7 +93,9 @@ __device__ inline int halo_pos(int h) {
 template <int LG, int LPN, int TX, int TY, int PREC>
 struct Smem {
   using G = Geometry<LG, LPN, TX, TY>;
-  typename MsgT<PREC>::T q[G::LP * G::PS];
+  // q as FP32 values of the message type (16-bit messages rounded where
+  // they are written): the stencil reads whole words in every precision
+  float q[G::LP * G::PS];
   float theta[G::LP * G::LS];
 };
 
@@ -320,14 +322,14 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
 #pragma unroll
   for (int j = 0; j < LG; ++j) {
     const int l = sub * LG + j;
-    sm.q[l * PS + p] = M::enc((inside && valid[j]) ? __expf(ell[j]) : 0.f);
+    sm.q[l * PS + p] = M::dec(M::enc((inside && valid[j]) ? __expf(ell[j]) : 0.f));
   }
 #pragma unroll
   for (int r = 0; r < HREG; ++r) {
     const int f = tid + r * NT;
     if (f < LP * HALO) {
       const int l = f / HALO;
-      sm.q[l * PS + halo_pos<TX, TY>(f - l * HALO)] = M::enc(__expf(hv[r]));   // exp(-inf) = 0
+      sm.q[l * PS + halo_pos<TX, TY>(f - l * HALO)] = M::dec(M::enc(__expf(hv[r])));   // exp(-inf) = 0
     }
   }
 #pragma unroll
@@ -342,9 +344,9 @@ __device__ inline void tile_step(const StepArgs& a, float one_minus_alpha, int b
   float S[LG];
 #pragma unroll
   for (int j = 0; j < LG; ++j) {
-    const typename M::T* q = sm.q + (sub * LG + j) * PS + p;
-    float s = M::dec(q[-HX]) + M::dec(q[-1]) + M::dec(q[1]) + M::dec(q[HX]);
-    if (CONN == 8) s += (M::dec(q[-HX - 1]) + M::dec(q[-HX + 1])) + (M::dec(q[HX - 1]) + M::dec(q[HX + 1]));
+    const float* q = sm.q + (sub * LG + j) * PS + p;
+    float s = q[-HX] + q[-1] + q[1] + q[HX];
+    if (CONN == 8) s += (q[-HX - 1] + q[-HX + 1]) + (q[HX - 1] + q[HX + 1]);
     S[j] = s;
   }
 
