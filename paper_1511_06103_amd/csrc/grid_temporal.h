@@ -290,8 +290,27 @@ struct MGeom {
   static constexpr int NOB = (LG + 3) / 4;            // output blocks of 16 rows
   static constexpr int RX = TX + 2 * K, RY = TY + 2 * K, RA = RX * RY;
   static constexpr int RN = mfma_plane_stride(RA);
-  static constexpr size_t lds = (size_t)RN * (2 * LP * sizeof(typename MsgT<PREC>::T) + NPL * 4);
+  static constexpr size_t lds_with(size_t qbytes) { return (size_t)RN * (2 * LP * qbytes + NPL * 4); }
+  // q in LDS as FP32 values of the message type (16-bit messages rounded
+  // where q is written) whenever both buffers fit that way; 16-bit words
+  // otherwise, where FP32 words would force a shallower launch.  The
+  // stencil reads whole words without a decode in the FP32 layout.
+  static constexpr bool QF = PREC == P_F32 || lds_with(4) <= kLdsMax;
+  using QT = typename std::conditional<QF, float, typename MsgT<PREC>::T>::type;
+  static constexpr size_t lds = lds_with(sizeof(QT));
 };
+
+// Store and load of a q value in either LDS layout (identity in FP32).
+template <class QT, class M>
+__device__ inline QT q_put(float v) {
+  if constexpr (std::is_same<QT, float>::value) return M::dec(M::enc(v));
+  else return M::enc(v);
+}
+template <class QT, class M>
+__device__ inline float q_get(QT v) {
+  if constexpr (std::is_same<QT, float>::value) return v;
+  else return M::dec(v);
+}
 
 // Global load at a 32-bit byte offset from a wavefront-uniform base (the
 // saddr + voffset form: no per-lane 64-bit address arithmetic).
@@ -304,7 +323,7 @@ __global__ __launch_bounds__((MGeom<LG, LC, PREC, TX, TY, K>::NT)) void multi_st
     StepArgs a, float one_minus_alpha, int ks) {
   using G = MGeom<LG, LC, PREC, TX, TY, K>;
   using M = MsgT<PREC>;
-  using T = typename M::T;
+  using T = typename G::QT;                 // q's word in LDS
   constexpr int NT = G::NT, NW = NT / 64, LP = G::LP, NPL = G::NPL, NOB = G::NOB;
   constexpr int RX = G::RX, RA = G::RA, RN = G::RN;
   constexpr int LOADS = (LP * RA + NT - 1) / NT;
@@ -366,7 +385,7 @@ __global__ __launch_bounds__((MGeom<LG, LC, PREC, TX, TY, K>::NT)) void multi_st
       const int l = f / RA;
       const int o = l * RN + (f - l * RA);
       if (l < NPL) ls[o] = v[r];
-      const T e = M::enc(__expf(v[r]));
+      const T e = q_put<T, M>(__expf(v[r]));
       qs[0][o] = e;
       qs[1][o] = e;
     }
@@ -484,9 +503,11 @@ __global__ __launch_bounds__((MGeom<LG, LC, PREC, TX, TY, K>::NT)) void multi_st
           // offsets from it (the opaque copy keeps the compiler from
           // re-deriving a base for each pair of reads)
           const T* qp = lds_ptr<T>(opaque(qb + (unsigned)(4 * j * RN) * (unsigned)sizeof(T)));
-          const float n0 = M::dec(qp[1]), w0 = M::dec(qp[RX]), e0 = M::dec(qp[RX + 2]), s0 = M::dec(qp[2 * RX + 1]);
+          const float n0 = q_get<T, M>(qp[1]), w0 = q_get<T, M>(qp[RX]), e0 = q_get<T, M>(qp[RX + 2]),
+                      s0 = q_get<T, M>(qp[2 * RX + 1]);
           float tot = (n0 + w0) + (e0 + s0);
-          if (CONN == 8) tot += (M::dec(qp[0]) + M::dec(qp[2])) + (M::dec(qp[2 * RX]) + M::dec(qp[2 * RX + 2]));
+          if (CONN == 8)
+            tot += (q_get<T, M>(qp[0]) + q_get<T, M>(qp[2])) + (q_get<T, M>(qp[2 * RX]) + q_get<T, M>(qp[2 * RX + 2]));
           S[j] = valid[j] ? tot : 0.f;
           // log q of a padding slot is never used; its plane exists only when NPL == LP
           const int eo = (NPL == LP || valid[j]) ? cb + 4 * j * RN : cc;
@@ -527,7 +548,7 @@ __global__ __launch_bounds__((MGeom<LG, LC, PREC, TX, TY, K>::NT)) void multi_st
           for (int j = 0; j < LG; ++j) {
             if (valid[j]) {
               ls[cb + 4 * j * RN] = z[j] - lse;
-              qn[cb + 4 * j * RN] = M::enc(e[j] * inv);
+              qn[cb + 4 * j * RN] = q_put<T, M>(e[j] * inv);
             }
           }
         }
