@@ -35,6 +35,18 @@ using lanes::group_sum;
 
 constexpr size_t kLdsMax = 160 * 1024;
 
+// Store and load of a q value in either LDS layout (identity in FP32).
+template <class QT, class M>
+__device__ inline QT q_put(float v) {
+  if constexpr (std::is_same<QT, float>::value) return M::dec(M::enc(v));
+  else return M::enc(v);
+}
+template <class QT, class M>
+__device__ inline float q_get(QT v) {
+  if constexpr (std::is_same<QT, float>::value) return v;
+  else return M::dec(v);
+}
+
 template <int LG, int LPN, int LC, int PREC, int TX, int TY, int K>
 struct TGeom {
   static constexpr int NT = TX * TY * LPN;            // threads per workgroup
@@ -45,8 +57,14 @@ struct TGeom {
   // (reading planes LG apart at the same position) hit different LDS banks
   static constexpr int RN = lanes::plane_stride<LG, LPN>(RX * RY);
   static constexpr int TS = (NPL + 3) & ~3;           // Theta row stride in LDS
-  static constexpr size_t lds = (size_t)NPL * RN * (2 * sizeof(typename MsgT<PREC>::T) + 4) +
-                                (size_t)NPL * TS * 4;
+  static constexpr size_t lds_with(size_t qbytes) {
+    return (size_t)NPL * RN * (2 * qbytes + 4) + (size_t)NPL * TS * 4;
+  }
+  // q in LDS as FP32 values of the message type whenever both buffers fit
+  // that way (as in MGeom below)
+  static constexpr bool QF = PREC == P_F32 || lds_with(4) <= kLdsMax;
+  using QT = typename std::conditional<QF, float, typename MsgT<PREC>::T>::type;
+  static constexpr size_t lds = lds_with(sizeof(QT));
 };
 
 
@@ -55,7 +73,7 @@ __global__ __launch_bounds__((TGeom<LG, LPN, LC, PREC, TX, TY, K>::NT)) void mul
     StepArgs a, float one_minus_alpha, int ks) {
   using G = TGeom<LG, LPN, LC, PREC, TX, TY, K>;
   using M = MsgT<PREC>;
-  using T = typename M::T;
+  using T = typename G::QT;                 // q's word in LDS
   constexpr int NT = G::NT, LP = G::LP, NPL = G::NPL, RX = G::RX, RN = G::RN, TS = G::TS;
   constexpr int RA = RX * G::RY;                       // region nodes (RN >= RA is the padded stride)
   constexpr int LOADS = (NPL * RA + NT - 1) / NT;
@@ -100,7 +118,7 @@ __global__ __launch_bounds__((TGeom<LG, LPN, LC, PREC, TX, TY, K>::NT)) void mul
       const int l = f / RA;
       const int o = l * RN + (f - l * RA);
       ls[o] = v[r];
-      const T e = M::enc(__expf(v[r]));
+      const T e = q_put<T, M>(__expf(v[r]));
       qs[0][o] = e;
       qs[1][o] = e;
     }
@@ -143,8 +161,9 @@ __global__ __launch_bounds__((TGeom<LG, LPN, LC, PREC, TX, TY, K>::NT)) void mul
 #pragma unroll
       for (int j = 0; j < LG; ++j) {
         const T* q = qc + pl[j] * RN + c;
-        float sum = M::dec(q[-RX]) + M::dec(q[-1]) + M::dec(q[1]) + M::dec(q[RX]);
-        if (CONN == 8) sum += (M::dec(q[-RX - 1]) + M::dec(q[-RX + 1])) + (M::dec(q[RX - 1]) + M::dec(q[RX + 1]));
+        float sum = q_get<T, M>(q[-RX]) + q_get<T, M>(q[-1]) + q_get<T, M>(q[1]) + q_get<T, M>(q[RX]);
+        if (CONN == 8)
+          sum += (q_get<T, M>(q[-RX - 1]) + q_get<T, M>(q[-RX + 1])) + (q_get<T, M>(q[RX - 1]) + q_get<T, M>(q[RX + 1]));
         S[j] = valid[j] ? sum : 0.f;
         ell[j] = ls[pl[j] * RN + c];
       }
@@ -200,7 +219,7 @@ __global__ __launch_bounds__((TGeom<LG, LPN, LC, PREC, TX, TY, K>::NT)) void mul
       for (int j = 0; j < LG; ++j) {
         if (valid[j]) {
           ls[pl[j] * RN + c] = z[j] - lse;
-          qn[pl[j] * RN + c] = M::enc(e[j] * inv);
+          qn[pl[j] * RN + c] = q_put<T, M>(e[j] * inv);
         }
       }
     }
@@ -299,18 +318,6 @@ struct MGeom {
   using QT = typename std::conditional<QF, float, typename MsgT<PREC>::T>::type;
   static constexpr size_t lds = lds_with(sizeof(QT));
 };
-
-// Store and load of a q value in either LDS layout (identity in FP32).
-template <class QT, class M>
-__device__ inline QT q_put(float v) {
-  if constexpr (std::is_same<QT, float>::value) return M::dec(M::enc(v));
-  else return M::enc(v);
-}
-template <class QT, class M>
-__device__ inline float q_get(QT v) {
-  if constexpr (std::is_same<QT, float>::value) return v;
-  else return M::dec(v);
-}
 
 // Global load at a 32-bit byte offset from a wavefront-uniform base (the
 // saddr + voffset form: no per-lane 64-bit address arithmetic).
