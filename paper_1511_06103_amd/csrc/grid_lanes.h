@@ -472,7 +472,9 @@ __global__ __launch_bounds__(TX * TY * LPN) void step_many_kernel(ManyArgs m) {
 // L = 21 they ran at 208 us per step against 222 us for 64 x 4 (64 x 8:
 // 215, 32 x 8: 218, 128 x 4: 243, 64 x 16: 275; shapes whose wavefront
 // count is not a multiple of the four SIMDs, 64 x 5 and 64 x 10, 258 and
-// 320 us).
+// 320 us).  Cache-resident grids take 64 x 8 tiles: on the 16 x 128 x 128,
+// L = 21 batch 18.9 us per step against 19.9 us for 64 x 4 (BF16 messages
+// 17.9 against 19.4), the same on 256 x 256.
 inline int slots_for(int L) {
   return L == 2 ? 2 : L == 21 ? 21 : L <= 4 ? 4 : L <= 8 ? 8 : L <= 16 ? 16 : 32;
 }
@@ -521,13 +523,14 @@ struct ForPrec {
     }
     return hipGetLastError();
   }
-  // Streaming launches take tiles three times as tall (64 x 12: twelve
-  // wavefronts, two workgroups and six wavefronts per SIMD at L = 21 where
-  // 64 x 4 fits four and four)
+  // Single-step launches take taller tiles than the batched kernel's 64 x 4:
+  // 64 x 12 when streaming (twelve wavefronts, two workgroups and six
+  // wavefronts per SIMD at L = 21 where 64 x 4 fits four and four), 64 x 8
+  // otherwise (half the halo rows per node at the same occupancy).
   template <int LG, int LPN, int LC, int TX, int TY>
   static hipError_t one(const StepArgs& a, int conn, int compat, hipStream_t s) {
     return streams_past_cache(a) ? one_s<LG, LPN, LC, TX, 3 * TY, true>(a, conn, compat, s)
-                                 : one_s<LG, LPN, LC, TX, TY, false>(a, conn, compat, s);
+                                 : one_s<LG, LPN, LC, TX, 2 * TY, false>(a, conn, compat, s);
   }
   template <int LG, int LPN, int LC, int TX, int TY>
   static hipError_t many(const ManyArgs& m, int conn, int compat, hipStream_t s) {
