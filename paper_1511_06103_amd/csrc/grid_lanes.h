@@ -462,8 +462,9 @@ __global__ __launch_bounds__(TX * TY * LPN) void step_many_kernel(ManyArgs m) {
   tile_step<LG, LPN, LC, CONN, COMPAT, PREC, TX, TY>(m.slot[k], m.one_minus_alpha[k], b, tx * TX, ty * TY, sm);
 }
 
-// Single-step kernels run one lane per node (LPN = 1) on 64 x 4 tiles: of
-// the label splits measured on the 256 x 256, L = 21 grid (1, 2 and 4 lanes
+// Single-step kernels run one lane per node (LPN = 1), the launch helpers
+// below taking 64 x 4 as the base tile (see ForPrec::one for the shapes
+// launched): of the label splits measured on the 256 x 256, L = 21 grid (1, 2 and 4 lanes
 // per node, 64 x 4 / 32 x 4 / 16 x 4 / 16 x 8 tiles) all took 10-13 us per
 // step there, while on the 2048 x 2048 grid one lane per node streamed
 // fastest (277 us per step against 346-508 us).  The label-parallel split
@@ -474,7 +475,8 @@ __global__ __launch_bounds__(TX * TY * LPN) void step_many_kernel(ManyArgs m) {
 // count is not a multiple of the four SIMDs, 64 x 5 and 64 x 10, 258 and
 // 320 us).  Cache-resident grids take 64 x 8 tiles: on the 16 x 128 x 128,
 // L = 21 batch 18.9 us per step against 19.9 us for 64 x 4 (BF16 messages
-// 17.9 against 19.4), the same on 256 x 256.
+// 17.9 against 19.4), the same on 256 x 256; the batched kernel's step
+// kernels in the 512-request serving replay 0.167 s against 0.175 s.
 inline int slots_for(int L) {
   return L == 2 ? 2 : L == 21 ? 21 : L <= 4 ? 4 : L <= 8 ? 8 : L <= 16 ? 16 : 32;
 }
@@ -489,7 +491,7 @@ inline bool streams_past_cache(const StepArgs& a) {
 
 inline int tiles(int B, int H, int W, int L) {
   (void)L;
-  return B * ((W + 63) / 64) * ((H + 3) / 4);
+  return B * ((W + 63) / 64) * ((H + 7) / 8);
 }
 
 hipError_t launch_f32(const StepArgs& a, int conn, int compat, hipStream_t s);
@@ -523,10 +525,10 @@ struct ForPrec {
     }
     return hipGetLastError();
   }
-  // Single-step launches take taller tiles than the batched kernel's 64 x 4:
-  // 64 x 12 when streaming (twelve wavefronts, two workgroups and six
-  // wavefronts per SIMD at L = 21 where 64 x 4 fits four and four), 64 x 8
-  // otherwise (half the halo rows per node at the same occupancy).
+  // Single-step launches take 64 x 12 tiles when streaming (twelve
+  // wavefronts, two workgroups and six wavefronts per SIMD at L = 21 where
+  // 64 x 4 fits four and four), 64 x 8 otherwise (half the halo rows per node
+  // of 64 x 4 at the same occupancy), as the batched kernel does.
   template <int LG, int LPN, int LC, int TX, int TY>
   static hipError_t one(const StepArgs& a, int conn, int compat, hipStream_t s) {
     return streams_past_cache(a) ? one_s<LG, LPN, LC, TX, 3 * TY, true>(a, conn, compat, s)
@@ -564,12 +566,12 @@ struct ForPrec {
   }
   static hipError_t launch_many(const ManyArgs& m, int L, int conn, int compat, hipStream_t s) {
     switch (slots_for(L)) {
-      case 2: return L == 2 ? many<2, 1, 2, 64, 4>(m, conn, compat, s) : many<2, 1, 0, 64, 4>(m, conn, compat, s);
-      case 21: return many<21, 1, 21, 64, 4>(m, conn, compat, s);
-      case 4: return many<4, 1, 0, 64, 4>(m, conn, compat, s);
-      case 8: return many<8, 1, 0, 64, 4>(m, conn, compat, s);
-      case 16: return many<16, 1, 0, 64, 4>(m, conn, compat, s);
-      default: return many<32, 1, 0, 64, 4>(m, conn, compat, s);
+      case 2: return L == 2 ? many<2, 1, 2, 64, 8>(m, conn, compat, s) : many<2, 1, 0, 64, 8>(m, conn, compat, s);
+      case 21: return many<21, 1, 21, 64, 8>(m, conn, compat, s);
+      case 4: return many<4, 1, 0, 64, 8>(m, conn, compat, s);
+      case 8: return many<8, 1, 0, 64, 8>(m, conn, compat, s);
+      case 16: return many<16, 1, 0, 64, 8>(m, conn, compat, s);
+      default: return many<32, 1, 0, 64, 8>(m, conn, compat, s);
     }
   }
 };
