@@ -274,6 +274,23 @@ def test_fused_steps_reduced_precision(c2, precision, tol, k):
     assert err <= tol * k, (precision, k, err)
 
 
+@pytest.mark.parametrize("precision,tol", [("bf16", 2e-3), ("f16", 2e-4)])
+@pytest.mark.parametrize("L", [13, 28, 32])
+def test_fused_four_steps_reduced_precision_label_counts(precision, tol, L):
+    """Four fused steps per launch with 16-bit messages at label counts whose
+    q buffers sit in LDS as FP32 words (L = 13) or as 16-bit words (L = 28
+    and 32, where FP32 words would not fit four steps): within the per-step
+    message-precision bound times the steps of the FP64 oracle."""
+    inst = synth.grid_theta_random(700 + L, 48, 80, L, synth.GRID8, alpha=0.5, iters=4)
+    s = cases.gpu_solver(inst, precision=precision, steps_per_launch=4)
+    assert s.steps_per_launch == 4
+    s.step(4)
+    assert s.check() is None
+    ref = O.solve(cases.oracle_model(inst), 0.5, 4)[-1]
+    err = cases.max_dq(gpu_state(s)[0], ref)
+    assert err <= 4 * tol, (precision, L, err)
+
+
 def test_batch16_workload_end_to_end():
     inst = synth.workload_c5()
     s = cases.gpu_solver(inst)
