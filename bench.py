@@ -79,6 +79,11 @@ WORKLOADS = {
     "csr_grid2048_L21": lambda s: s.grid_as_csr(s.workload_big()),
 }
 ADJOINT_CKPT = 5
+# Solver options per workload and message precision: the grid as CSR keeps a
+# grid's node order, so neighbours sit close and with FP32 rows one lane per
+# node (whole rows per load) gathers fastest; 16-bit rows and random graphs
+# keep the library's two lanes.
+SOLVER_OPTIONS = {("csr_grid2048_L21", "f32"): {"csr_lanes": 1}}
 
 
 def log(*a):
@@ -503,6 +508,8 @@ def main():
                     help="--mode kernel: steps per launch (default: the library's choice)")
     ap.add_argument("--warm-launches", type=int, default=2,
                     help="--mode kernel: untimed launches before the timed ones")
+    ap.add_argument("--csr-lanes", type=int, default=None, choices=[0, 1, 2],
+                    help="general graphs: lanes per node (default: the workload's setting)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -535,7 +542,10 @@ def main():
             sys.exit("the adjoint runs with FP32 messages only")
         return bench_adjoint(args, inst, torch, mf)
     extra = {} if args.mode != "kernel" or args.steps_per_launch is None else {"steps_per_launch": args.steps_per_launch}
-    solver = make_solver(inst, torch, mf, precision=args.precision, **extra)
+    options = dict(SOLVER_OPTIONS.get((args.workload, args.precision), {}))
+    if args.csr_lanes is not None:
+        options["csr_lanes"] = args.csr_lanes
+    solver = make_solver(inst, torch, mf, precision=args.precision, **extra, **options)
     q = torch.empty_like(solver.unary)
 
     if args.mode == "kernel":
@@ -616,7 +626,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict(workload_config(inst, "init + iters proximal steps + write q"), messages=args.precision),
+        "config": dict(workload_config(inst, "init + iters proximal steps + write q"), messages=args.precision,
+                       **options),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

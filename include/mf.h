@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define MF_ABI_VERSION 3
+#define MF_ABI_VERSION 4
 /* Largest label count: grids with the fixed-step rule take up to 128 labels
    (above 32 one step per launch, Theta S on the matrix cores); CSR and dense
    graphs, the other step rules, mf_step_many's shared launches, the adjoint
@@ -182,6 +182,15 @@ typedef struct mf_desc {
   void *workspace;         /* device scratch of at least mf_workspace_size bytes */
   size_t workspace_bytes;
   void *stream;            /* hipStream_t */
+  /* General graphs: lanes that gather one node's neighbour rows.  0 = the
+   * library's choice (two for L > 12, one otherwise), 1 = one, 2 = two where
+   * L > 12; any other value is MF_EINVAL.  One lane per node loads each row
+   * whole in fewer, wider loads: faster where the node order keeps neighbours
+   * close (the 2048 x 2048 grid as CSR, L = 21, FP32: 479 against 554 us
+   * per step), slower on graphs without locality (a random graph of 2^20
+   * nodes: 308 against 288 us) and with 16-bit messages.  Ignored for grids
+   * and dense graphs. */
+  int32_t csr_lanes;
 } mf_desc;
 
 typedef struct mf_handle mf_handle;

@@ -363,9 +363,8 @@ __global__ __launch_bounds__(kCsrThreads) void csr_fe_kernel(CsrFreeEnergyArgs a
   if (threadIdx.x == 0) a.partials[(size_t)b * a.n_blocks + blockIdx.x] = t;
 }
 
-template <int LQ, int LC, int PREC>
-hipError_t csr_step_prec(const CsrStepArgs& a, int compat, hipStream_t s) {
-  constexpr int P = LQ >= 16 ? 2 : 1;
+template <int LQ, int LC, int PREC, int P>
+hipError_t csr_step_lanes(const CsrStepArgs& a, int compat, hipStream_t s) {
   dim3 grid((unsigned)(((size_t)a.N * P + kCsrThreads - 1) / kCsrThreads), a.B);
   const float om = (float)(1.0 - (double)a.alpha);
   if (compat == MF_COMPAT_POTTS)
@@ -373,6 +372,16 @@ hipError_t csr_step_prec(const CsrStepArgs& a, int compat, hipStream_t s) {
   else
     hipLaunchKernelGGL((csr_step_kernel<LQ, LC, MF_COMPAT_GENERAL, P, PREC>), grid, dim3(kCsrThreads), 0, s, a, om);
   return hipGetLastError();
+}
+
+// Two lanes per node above 12 labels unless the descriptor asks for one
+// (mf_desc.csr_lanes = 1).
+template <int LQ, int LC, int PREC>
+hipError_t csr_step_prec(const CsrStepArgs& a, int compat, hipStream_t s) {
+  if constexpr (LQ >= 16) {
+    if (a.lanes != 1) return csr_step_lanes<LQ, LC, PREC, 2>(a, compat, s);
+  }
+  return csr_step_lanes<LQ, LC, PREC, 1>(a, compat, s);
 }
 
 template <int LQ, int LC>

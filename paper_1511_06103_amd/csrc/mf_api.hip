@@ -170,6 +170,7 @@ mf_status check_desc(const mf_desc* d, std::string* msg) {
     *msg = "general graphs: n_nodes * (n_labels rounded up to 4 or 8) * 4 bytes must be below 2^32";
     return MF_EUNSUPPORTED;
   }
+  if (d->csr_lanes < 0 || d->csr_lanes > 2) return bad("csr_lanes must be 0, 1 or 2");
   if (d->graph == MF_CSR) {
     if (!d->csr_row_ptr) return bad("csr_row_ptr is NULL");
     if (d->csr_nnz < 0 || d->csr_nnz > INT32_MAX) return bad("csr_nnz out of range");
@@ -360,6 +361,7 @@ mf_status enqueue_csr_steps(mf_handle* h, int n) {
     a.state_out = buf(h, h->cur ^ 1);
     a.q_in = csr_q(h, h->cur);
     a.q_out = csr_q(h, h->cur ^ 1);
+    a.lanes = d.csr_lanes;
     a.row_ptr = d.csr_row_ptr;
     a.col = d.csr_col;
     a.w = d.csr_w;

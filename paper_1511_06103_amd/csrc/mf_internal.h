@@ -65,6 +65,7 @@ struct CsrStepArgs {
   int B, L, N;
   float alpha;
   float potts_w;
+  int lanes;               // mf_desc.csr_lanes: 1 = one lane per node; otherwise the default
 };
 
 struct CsrFreeEnergyArgs {

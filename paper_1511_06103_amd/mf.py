@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")
 
-MF_ABI_VERSION = 3
+MF_ABI_VERSION = 4
 MF_MAX_LABELS = 128   # grids with the fixed-step rule; 32 elsewhere
 MF_SMALL_LABELS = 32
 MF_STATIC_SCRATCH_BYTES = 64 << 20   # scratch array of mf_solve_static, per GPU
@@ -56,6 +56,7 @@ class MFDesc(ctypes.Structure):
         ("unary", ctypes.c_void_p), ("theta", ctypes.c_void_p), ("state", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+        ("csr_lanes", ctypes.c_int32),
     ]
 
 
@@ -208,7 +209,7 @@ class MeanField:
                  cooc: Optional[torch.Tensor] = None, state: Optional[torch.Tensor] = None,
                  stream: Optional[torch.cuda.Stream] = None, steps_per_launch: int = 0,
                  rule: str = "fixed", gamma1: Optional[float] = None, gamma2: float = 0.999,
-                 eps: float = 1e-8, v0: float = 1.0):
+                 eps: float = 1e-8, v0: float = 1.0, csr_lanes: int = 0):
         L_ = lib()
         self._handle = None
         u = _dev_tensor(unary, torch.float32, "unary", None)
@@ -246,6 +247,7 @@ class MeanField:
         d.alpha = float(alpha)
         d.potts_w = 0.0 if potts_w is None else float(potts_w)
         d.steps_per_launch = int(steps_per_launch)
+        d.csr_lanes = int(csr_lanes)
         if rule not in RULES:
             raise ValueError(f"unknown step rule {rule!r}")
         d.rule = RULES[rule]

@@ -179,6 +179,8 @@ def test_csr_gathered_rows_limit():
 
 def test_csr_descriptor_validation():
     assert validate(csr_desc()) == mf.MF_OK
+    for lanes, want in ((0, mf.MF_OK), (1, mf.MF_OK), (2, mf.MF_OK), (3, mf.MF_EINVAL), (-1, mf.MF_EINVAL)):
+        assert validate(csr_desc(csr_lanes=lanes)) == want, lanes
     assert validate(csr_desc(csr_w=FAKE + (1 << 38))) == mf.MF_OK
     assert validate(csr_desc(csr_nnz=0, csr_col=None)) == mf.MF_OK      # no edges
     assert validate(csr_desc(csr_row_ptr=None)) == mf.MF_EINVAL

@@ -34,9 +34,12 @@ def gpu_state(s):
     (4096, 13, 12, False, 1),
     (1500, 17, 7, True, 1),
 ])
-def test_csr_end_to_end(n, L, deg, weighted, B):
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_csr_end_to_end(n, L, deg, weighted, B, lanes):
+    """Both gather layouts (csr_lanes: the library's choice, or one lane per
+    node, which differs from it above 12 labels)."""
     inst = synth.csr_instance(40 + n + L, n, L, deg, weighted, alpha=0.5, iters=10, batch=B)
-    s = cases.gpu_solver(inst)
+    s = cases.gpu_solver(inst, csr_lanes=lanes)
     g0 = gpu_state(s)
     for b in range(B):
         np.testing.assert_allclose(np.exp(g0[b]), np.exp(O.init_state(inst.unary[b].astype(np.float64))),
@@ -93,7 +96,8 @@ def rounding(precision):
 
 @pytest.mark.parametrize("precision,tol", [("bf16", 2e-3), ("f16", 2e-4)])
 @pytest.mark.parametrize("L", [4, 13, 21])
-def test_csr_message_precision_one_step(L, precision, tol):
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_csr_message_precision_one_step(L, precision, tol, lanes):
     """The BF16 / FP16 message modes round q to 16 bits where it is gathered
     (one lane per node at L = 4, two at L = 13 and 21).  One step from an
     identical state is within the operand-rounding bound of the FP64 step, as
@@ -107,7 +111,7 @@ def test_csr_message_precision_one_step(L, precision, tol):
     B, _, N = inst.unary.shape
     st = torch.empty((2, B, L, N), dtype=torch.float32, device="cuda:0")
     st[0].copy_(torch.from_numpy(start[None]))
-    s = cases.gpu_solver(inst, init="state", state=st, precision=precision)
+    s = cases.gpu_solver(inst, init="state", state=st, precision=precision, csr_lanes=lanes)
     s.step(1)
     g = gpu_state(s)[0]
     ref = O.prox_step(start.astype(np.float64), model, 0.5)
@@ -207,13 +211,14 @@ def test_malformed_csr_reported_without_fault(defect):
     assert e.value.status == mf.MF_EINVAL
 
 
-def test_csr_grid2048_one_step_sampled_rows():
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_csr_grid2048_one_step_sampled_rows(lanes):
     """The 2048 x 2048, L = 21 grid as a CSR graph (the beyond-cache CSR
-    benchmark): one step against the oracle on row bands at the top, the
-    middle and the bottom, the full width."""
+    benchmark, in both gather layouts): one step against the oracle on row
+    bands at the top, the middle and the bottom, the full width."""
     ginst = synth.workload_big()
     inst = synth.grid_as_csr(ginst)
-    s = cases.gpu_solver(inst)
+    s = cases.gpu_solver(inst, csr_lanes=lanes)
     s.step(1)
     g = gpu_state(s)[0].reshape(21, 2048, 2048)
     u = ginst.unary[0].astype(np.float64).reshape(21, 2048, 2048)
