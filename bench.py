@@ -318,10 +318,11 @@ def cpu_baseline(inst, budget_s=8.0):
             "host": {"cpu_count": os.cpu_count(), "cpu_model": cpu_model()}}
 
 
-def load_counters(workload, k, kind, precision="f32"):
-    """The rocprofv3 readings of the dominant kernel for this workload, launch
-    depth and message precision (profiles/step_kernel_traffic.json), or None
-    when none were taken or the kernel's sources changed since."""
+def load_counters(workload, k, kind, precision="f32", options=None):
+    """The rocprofv3 readings of the dominant kernel for this workload (the
+    name bench.py runs it under), launch depth, message precision and solver
+    options (profiles/step_kernel_traffic.json), or None when none were taken
+    or the kernel's sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -330,6 +331,7 @@ def load_counters(workload, k, kind, precision="f32"):
     for e in t.get("entries", []):
         if (e.get("workload") == workload and e.get("steps_per_launch") == k
                 and e.get("precision", "f32") == precision
+                and e.get("options", {}) == (options or {})
                 and e.get("kernel_source_sha256_16") == source_hash(kind)):
             return e
     return None
@@ -588,7 +590,7 @@ def main():
     lib_k = solver.steps_per_launch
     mean_d, k = time_step_launches(solver, torch, args.launches, iters=T)
     kname = step_kernel_name(inst, k, lib_k)
-    counters = load_counters(inst.name, k, source_kind(inst, lib_k), args.precision)
+    counters = load_counters(args.workload, k, source_kind(inst, lib_k), args.precision, options)
     roofline = roofline_object(inst, k, args.precision, mean_d, args.launches, kname, counters)
     log(f"{kname} (K={k}): {mean_d * 1e6:.2f} us mean per launch over {args.launches} back-to-back "
         f"launches -> {roofline['hbm']['achieved']:.0f} GB/s algorithmic; bound {roofline['bound']} "
