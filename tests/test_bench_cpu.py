@@ -54,6 +54,27 @@ def test_traffic_used_only_for_current_sources(tmp_path, monkeypatch):
     assert bench.load_traffic("w", 1, kind) is None
 
 
+def test_counters_match_the_solver_options(tmp_path, monkeypatch):
+    """An entry taken with solver options (one lane per node on the grid as
+    CSR) serves only runs with those options, and every committed entry
+    belongs to a workload bench.py runs, under its workload name."""
+    kind = "csr"
+    entry = {"workload": "w", "steps_per_launch": 1, "options": {"csr_lanes": 1},
+             "kernel_source_sha256_16": bench.source_hash(kind), "hbm_bytes_per_launch": 99}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({"entries": [entry]}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.load_counters("w", 1, kind, "f32", {"csr_lanes": 1})["hbm_bytes_per_launch"] == 99
+    assert bench.load_counters("w", 1, kind, "f32", {}) is None
+    assert bench.load_counters("w", 1, kind, "f32", {"csr_lanes": 2}) is None
+    with open(os.path.join(ROOT, "profiles", "step_kernel_traffic.json")) as f:
+        committed = json.load(f)["entries"]
+    for e in committed:
+        assert e["workload"] in bench.WORKLOADS, e["workload"]
+        opts = bench.SOLVER_OPTIONS.get((e["workload"], e.get("precision", "f32")), {})
+        assert e.get("options", {}) == opts, (e["workload"], e.get("precision"))
+
+
 @pytest.mark.parametrize("kind", sorted(bench.KERNEL_SOURCES))
 def test_source_hash_covers_existing_files(kind):
     h = bench.source_hash(kind)
