@@ -193,9 +193,12 @@ def test_csr_without_edges_is_the_unary_closed_form():
 
 
 @pytest.mark.parametrize("defect", ["col_out_of_range", "row_ptr_decreasing", "row_ptr_end"])
-def test_malformed_csr_reported_without_fault(defect):
+@pytest.mark.parametrize("L,lanes", [(3, 0), (21, 0), (21, 1)])
+def test_malformed_csr_reported_without_fault(defect, L, lanes):
+    """A malformed CSR is stepped with clamped accesses and reported, in
+    every gather layout (one lane per node at L = 3; two or one at L = 21)."""
     from paper_1511_06103_amd import mf
-    inst = synth.csr_instance(9, 200, 3, 4, False)
+    inst = synth.csr_instance(9, 200, L, 4, False)
     row_ptr, col = inst.row_ptr.copy(), inst.col.copy()
     if defect == "col_out_of_range":
         col[5] = 200 + 7
@@ -204,7 +207,7 @@ def test_malformed_csr_reported_without_fault(defect):
     else:
         row_ptr[-1] = row_ptr[-1] - 1
     inst.row_ptr, inst.col = row_ptr, col
-    s = cases.gpu_solver(inst)
+    s = cases.gpu_solver(inst, csr_lanes=lanes)
     s.step(2)                       # runs with clamped accesses
     with pytest.raises(mf.MFError) as e:
         s.check()
