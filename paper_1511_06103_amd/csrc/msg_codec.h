@@ -26,7 +26,14 @@ template <> struct MsgT<P_BF16> {
 };
 template <> struct MsgT<P_F16> {
   using T = _Float16;
-  __device__ static T enc(float x) { return (T)x; }
+  // The FP32 value is rounded to FP16: the empty asm keeps the compiler from
+  // folding the product that formed x into one mixed-precision FMA rounded
+  // once to FP16, which it would do at some call sites and not at others,
+  // so every kernel stores the same bits for the same x.
+  __device__ static T enc(float x) {
+    asm("" : "+v"(x));
+    return (T)x;
+  }
   __device__ static float dec(T x) { return (float)x; }
 };
 
