@@ -236,3 +236,62 @@ def test_csr_grid2048_one_step_sampled_rows(lanes):
         b = h - 1 if hi < 2048 else h
         err = cases.max_dq(g[:, lo:hi, :][:, a:b, :].reshape(21, -1), ref[:, a:b, :].reshape(21, -1))
         assert err <= 1e-6, (y0, err)
+
+
+def skewed_degree_instance(L, seed=11, n=3000):
+    """A graph whose degrees span four orders of magnitude: a hub joined to
+    every node but 50 isolated ones (weights 0.01, so its messages stay of
+    order one), a 1000-node chain, a node of degree 100, and the rest
+    reached only through the hub; symmetric, rows sorted."""
+    rng = np.random.default_rng(seed)
+    hub, isolated = 7, set(range(100, 150))
+    und = {}
+    for j in range(n):
+        if j != hub and j not in isolated:
+            und[(min(hub, j), max(hub, j))] = 0.01
+    for j in range(1000, 1999):
+        und[(j, j + 1)] = float(rng.uniform(0.5, 1.5))
+    for j in range(2400, 2500):
+        und[(j, 2500)] = float(rng.uniform(0.5, 1.5))
+    rows = [[] for _ in range(n)]
+    for (a, b), w in und.items():
+        rows[a].append((b, w))
+        rows[b].append((a, w))
+    row_ptr = np.zeros(n + 1, np.int32)
+    col, wt = [], []
+    for i in range(n):
+        r = sorted(rows[i])
+        row_ptr[i + 1] = row_ptr[i] + len(r)
+        col += [c for c, _ in r]
+        wt += [w for _, w in r]
+    base = synth.csr_instance(seed, n, L, 4, True)
+    return synth.Instance(name=f"skewed{n}_L{L}", graph=synth.CSR, n_labels=L, n_nodes=n,
+                          unary=base.unary, theta=base.theta, compat=base.compat, alpha=0.5, iters=10,
+                          row_ptr=row_ptr, col=np.asarray(col, np.int32), csr_w=np.asarray(wt, np.float32))
+
+
+@pytest.mark.parametrize("L", [5, 21])
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_csr_skewed_degrees(L, lanes):
+    """Degree N - 51 next to degrees 0, 1, 2 and 100 in one launch: each
+    node's gather loop runs its own trip count (two lanes of a node, or one),
+    ten steps against the oracle within max(1e-5, twice the FP32 oracle's own
+    deviation from the FP64 one)."""
+    inst = skewed_degree_instance(L)
+    deg = np.diff(inst.row_ptr)
+    assert deg.max() == 2949 and (deg == 0).sum() == 50 and deg[2500] == 101
+    model = cases.oracle_model(inst)
+    ref = O.solve(model, 0.5, 10)[-1]
+    floor = cases.max_dq(O.solve(model.astype(np.float32), np.float32(0.5), 10)[-1], ref)
+    s = cases.gpu_solver(inst, csr_lanes=lanes)
+    s.step(10)
+    g = gpu_state(s)[0]
+    err = cases.max_dq(g, ref)
+    print(f"L={L} lanes={lanes} max|dq|={err:.3g} fp32 floor={floor:.3g}")
+    assert err <= max(1e-5, 2.0 * floor)
+    # the isolated nodes follow the closed form of an edgeless node
+    ell0 = O.init_state(inst.unary[0].astype(np.float64))
+    c = 0.5 ** 10
+    iso = O.normalise(c * ell0 - (1 - c) * inst.unary[0].astype(np.float64))[:, 100:150]
+    assert cases.max_dq(g[:, 100:150], iso) <= 1e-6
+    s.check()
