@@ -295,3 +295,60 @@ def test_csr_skewed_degrees(L, lanes):
     iso = O.normalise(c * ell0 - (1 - c) * inst.unary[0].astype(np.float64))[:, 100:150]
     assert cases.max_dq(g[:, 100:150], iso) <= 1e-6
     s.check()
+
+
+def test_csr_largest_gathered_rows_sampled():
+    """The largest CSR problem at L = 21 whose gathered rows fit the 32-bit
+    offsets: the 5460 x 8192 grid as a CSR graph (44.7 M nodes, 358 M edges,
+    96-byte q rows: N x 96 B within 0.025 % of 2^32), built on the device in
+    raster order with unit weights.  The unaries come from a seeded device
+    generator (logits 2 N(0, 1), u = -log_softmax); the initialisation and
+    one step, in both gather layouts, are checked against the oracle at
+    sampled nodes, the first and last rows included."""
+    from paper_1511_06103_amd import mf
+    H, W, L = 5460, 8192, 21
+    N = H * W
+    assert N * 96 < 1 << 32 and N * 96 > (1 << 32) - (1 << 21) and L * N < 1 << 30
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(23)
+    u = -torch.log_softmax(2.0 * torch.randn((1, L, N), generator=gen, device=dev), dim=1)
+    n = torch.arange(N, device=dev, dtype=torch.int64)
+    y, x = n // W, n % W
+    cols, valid = [], []
+    for dy, dx in [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 1), (1, -1), (1, 0), (1, 1)]:
+        yy, xx = y + dy, x + dx
+        valid.append((yy >= 0) & (yy < H) & (xx >= 0) & (xx < W))
+        cols.append(yy * W + xx)
+    valid, cols = torch.stack(valid, 1), torch.stack(cols, 1)
+    col = cols[valid].to(torch.int32).contiguous()
+    row_ptr = torch.zeros(N + 1, dtype=torch.int32, device=dev)
+    row_ptr[1:] = torch.cumsum(valid.sum(1), 0).to(torch.int32)
+    del n, y, x, cols, valid
+    th = np.triu(np.random.default_rng(24).uniform(0.0, 2.0, (L, L)), 1)
+    th = (th + th.T).astype(np.float32)
+    rng = np.random.default_rng(25)
+    ys = np.concatenate([rng.integers(0, H, 200), [0, 0, H - 1, H - 1, H - 2, H // 2]])
+    xs = np.concatenate([rng.integers(0, W, 200), [0, W - 1, 0, W - 1, W - 1, 0]])
+    idx = torch.from_numpy((ys * W + xs).astype(np.int64)).to(dev)
+    refs = []
+    for y0_, x0_ in zip(ys, xs):
+        y0, y1, x0, x1 = max(0, y0_ - 1), min(H, y0_ + 2), max(0, x0_ - 1), min(W, x0_ + 2)
+        nodes = (np.arange(y0, y1)[:, None] * W + np.arange(x0, x1)[None, :]).ravel()
+        uu = u[0][:, torch.from_numpy(nodes).to(dev)].cpu().numpy().astype(np.float64)
+        ell0 = O.init_state(uu)
+        c = (y0_ - y0) * (x1 - x0) + (x0_ - x0)
+        sub = O.grid_model(uu, y1 - y0, x1 - x0, 8, theta=th.astype(np.float64))
+        refs.append((ell0[:, c], O.prox_step(ell0.astype(np.float32).astype(np.float64), sub, 0.5)[:, c]))
+    for lanes in (0, 1):
+        s = mf.MeanField(u, "csr", theta=torch.from_numpy(th).to(dev), alpha=0.5, csr_row_ptr=row_ptr,
+                         csr_col=col, csr_lanes=lanes)
+        torch.cuda.synchronize()
+        got0 = s.current_state()[0][:, idx].cpu().numpy().astype(np.float64)
+        s.step(1)
+        got1 = s.current_state()[0][:, idx].cpu().numpy().astype(np.float64)
+        s.check()
+        s.close()
+        worst0 = max(cases.max_dq(got0[:, k], r0) for k, (r0, _) in enumerate(refs))
+        worst1 = max(cases.max_dq(got1[:, k], r1) for k, (_, r1) in enumerate(refs))
+        print(f"lanes={lanes} init {worst0:.3g} step {worst1:.3g}")
+        assert worst0 <= 1e-6 and worst1 <= 1e-6, (lanes, worst0, worst1)
