@@ -10,6 +10,8 @@
   rounded the same way where the rounding is compounded;
 * the initialisation and the FP64 free energy (1e-10 relative);
 * the 512 x 512, L = 128 benchmark shape at one step, on sampled rows;
+* the largest problem a handle accepts (L * N just below 2^30) at sampled
+  nodes;
 * continuous batching: a many-label handle stepped by mf_step_many equals
   the same handle stepped alone.
 """
@@ -192,3 +194,45 @@ def test_many_labels_rejected_where_not_implemented():
     with pytest.raises(mf.MFError) as e:
         s.lipschitz(v, v, 10)
     assert e.value.status == mf.MF_EUNSUPPORTED
+
+
+def test_largest_many_label_problem_sampled():
+    """The largest many-label problem a handle accepts: L = 128 on 2047 x
+    4097 nodes, L * N within 0.025 % of 2^30 (4.29 GB per array), so the
+    kernel's 32-bit byte offsets come within 0.03 % of 2^32; neither side is
+    a multiple of the tile.  Unaries from a seeded device generator (logits
+    2 N(0, 1), u = -log_softmax); the initialisation and one step in FP32
+    against the oracle at sampled nodes, corners and last row included."""
+    from paper_1511_06103_amd import mf
+    H, W, L = 2047, 4097, 128
+    N = H * W
+    assert L * N < 1 << 30 and L * N > (1 << 30) - (1 << 19)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(26)
+    u = -torch.log_softmax(2.0 * torch.randn((1, L, N), generator=gen, device=dev), dim=1)
+    th = np.triu(np.random.default_rng(27).uniform(0.0, 2.0, (L, L)), 1)
+    th = (th + th.T).astype(np.float32)
+    s = mf.MeanField(u, "grid8", height=H, width=W, theta=torch.from_numpy(th).to(dev), alpha=0.5)
+    rng = np.random.default_rng(28)
+    ys = np.concatenate([rng.integers(0, H, 150), [0, 0, H - 1, H - 1, H - 2, H // 2]])
+    xs = np.concatenate([rng.integers(0, W, 150), [0, W - 1, 0, W - 1, W - 1, W - 2]])
+    idx = torch.from_numpy((ys * W + xs).astype(np.int64)).to(dev)
+    torch.cuda.synchronize()
+    got0 = s.current_state()[0][:, idx].cpu().numpy().astype(np.float64)
+    s.step(1)
+    got1 = s.current_state()[0][:, idx].cpu().numpy().astype(np.float64)
+    s.check()
+    s.close()
+    worst0 = worst1 = 0.0
+    for k, (y, x) in enumerate(zip(ys, xs)):
+        y0, y1, x0, x1 = max(0, y - 1), min(H, y + 2), max(0, x - 1), min(W, x + 2)
+        nodes = (np.arange(y0, y1)[:, None] * W + np.arange(x0, x1)[None, :]).ravel()
+        uu = u[0][:, torch.from_numpy(nodes).to(dev)].cpu().numpy().astype(np.float64)
+        ell0 = O.init_state(uu)
+        c = (y - y0) * (x1 - x0) + (x - x0)
+        worst0 = max(worst0, cases.max_dq(got0[:, k], ell0[:, c]))
+        sub = O.grid_model(uu, y1 - y0, x1 - x0, 8, theta=th.astype(np.float64))
+        ref = O.prox_step(ell0.astype(np.float32).astype(np.float64), sub, 0.5)
+        worst1 = max(worst1, cases.max_dq(got1[:, k], ref[:, c]))
+    print(f"init {worst0:.3g} step {worst1:.3g}")
+    assert worst0 <= 1e-6 and worst1 <= ONE_STEP["f32"], (worst0, worst1)
