@@ -275,7 +275,8 @@ __global__ __launch_bounds__(kNT) void dense_epilogue_kernel(DenseStepArgs a, fl
     // column sums: label tid % 32, blocks tid / 32 + 16 k in order
     const int lt = tid % kLP;
     float t = 0.f;
-#pragma unroll 4
+    // 16 loads per trip: one round trip for the 256 blocks of 4096 nodes
+#pragma unroll 16
     for (int k = tid / kLP; k < a.NEB; k += kNT / kLP) t += a.t_in[((size_t)b * a.NEB + k) * kLP + lt];
     Tp[tid] = t;
   }
