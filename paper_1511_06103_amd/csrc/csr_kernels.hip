@@ -199,22 +199,33 @@ __global__ __launch_bounds__(kCsrThreads) void csr_step_kernel(CsrStepArgs a, fl
   e0 = e0 < 0 ? 0 : e0;
   e1 = e1 > nnz ? nnz : e1;
   // EB edges per trip: their column indices, then their q rows, are loaded
-  // together.  Edges past the row end (and out-of-range columns) get weight
-  // 0 and a valid address; the products are added in edge order.
+  // together, and the next trip's column indices and weights are in flight
+  // with this trip's q rows (one round trip per trip after the first).
+  // Edges past the row end (and out-of-range columns) get weight 0 and a
+  // valid address; the products are added in edge order.
   constexpr int EB = 4;
+  int jn[EB];
+  float wn[EB];
+  auto load_cols = [&](int e) {
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const bool on = e + u < e1;
+      const unsigned ec = (unsigned)(on ? e + u : e0) * 4u;   // called only when e0 < e1
+      jn[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(rc, ec, 0u, 0);
+      wn[u] = on ? (a.w ? rd32(rw, ec) : 1.f) : 0.f;
+    }
+  };
+  if (e0 < e1) load_cols(e0);
   for (int e = e0; e < e1; e += EB) {
     int j[EB];
     float w[EB];
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
-      const bool on = e + u < e1;
-      const unsigned ec = (unsigned)(on ? e + u : e0) * 4u;
-      const int jj = (int)__builtin_amdgcn_raw_buffer_load_b32(rc, ec, 0u, 0);
-      const float ww = a.w ? rd32(rw, ec) : 1.f;
-      const bool ok = on && jj >= 0 && jj < N;
-      j[u] = ok ? jj : 0;
-      w[u] = ok ? ww : 0.f;
+      const bool ok = e + u < e1 && jn[u] >= 0 && jn[u] < N;
+      j[u] = ok ? jn[u] : 0;
+      w[u] = ok ? wn[u] : 0.f;
     }
+    if (e + EB < e1) load_cols(e + EB);
     C v[EB][LH / 4];
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
